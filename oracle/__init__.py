@@ -1,0 +1,367 @@
+"""CPU oracle for the FCIQMC hot path of the Rimu.jl paper (arXiv 2601.19505).
+
+TEST INFRASTRUCTURE ONLY: a plain, serial, slow and obviously correct
+reference.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it.  It shares no code with
+the GPU library in ``paper_2601_19505_amd``; the two meet only through the
+seeded input generators in ``synthetic``.
+
+Contents (paper sections in brackets):
+
+* Fock addresses, dimension and combinatorial ranking [Sec. 2, Sec. 6.1]
+* real- and momentum-space 1D Bose-Hubbard columns [Sec. 2, Sec. 6.2, 6.3]
+* Philox4x32-10 counter-based draws (published definition, Salmon et al.)
+* one serial FCIQMC step and repeated steps [Sec. 3.1, 3.2, 7.1]
+* sparse-matrix and matrix-free Lanczos exact diagonalisation [Sec. 5]
+* blocking analysis, shift estimator, ratio of means [Sec. 4] (``stats``)
+
+Parity status of every function is listed in the design doc; every function here
+is pinned by a ``-m "not gpu"`` test against the paper's printed values,
+closed forms or independent library routines.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+REAL1D = 0
+MOM1D = 1
+
+
+class Ham(C.Structure):
+    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("pad", C.c_int32),
+                ("t", C.c_double), ("u", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("h", Ham), ("dtau", C.c_double), ("target", C.c_double), ("zeta", C.c_double),
+                ("xi", C.c_double), ("theta", C.c_double), ("t_rel", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("len", C.c_int64), ("exact_steps", C.c_int64),
+                ("inexact_steps", C.c_int64), ("spawns", C.c_int64), ("shift", C.c_double),
+                ("norm", C.c_double), ("hproj", C.c_double), ("vproj", C.c_double)]
+
+
+EVENT_DTYPE = np.dtype([("parent", np.int64), ("attempt", np.int64), ("dest", np.uint64, (2,)),
+                        ("value", np.float64)])
+STATS_FIELDS = [f for f, _ in Stats._fields_]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        u64p, f64p, i64p, i32p, u32p = (P(C.c_uint64), P(C.c_double), P(C.c_int64), P(C.c_int32),
+                                        P(C.c_uint32))
+        L.orc_binom.restype = C.c_uint64
+        L.orc_binom.argtypes = [C.c_int, C.c_int]
+        L.orc_dimension.restype = C.c_uint64
+        L.orc_dimension.argtypes = [C.c_int, C.c_int]
+        L.orc_encode.restype = C.c_int
+        L.orc_encode.argtypes = [i32p, C.c_int, u64p]
+        L.orc_decode.restype = None
+        L.orc_decode.argtypes = [u64p, C.c_int, C.c_int, i32p]
+        L.orc_rank.restype = C.c_uint64
+        L.orc_rank.argtypes = [u64p, C.c_int, C.c_int]
+        L.orc_unrank.restype = None
+        L.orc_unrank.argtypes = [C.c_uint64, C.c_int, C.c_int, u64p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_draw.restype = None
+        L.orc_draw.argtypes = [C.c_uint64, u64p, C.c_uint32, C.c_uint32, C.c_uint32, u32p]
+        L.orc_det_log.restype = C.c_double
+        L.orc_det_log.argtypes = [C.c_double]
+        L.orc_fsum.restype = C.c_double
+        L.orc_fsum.argtypes = [f64p, C.c_int64]
+        L.orc_column.restype = C.c_int
+        L.orc_column.argtypes = [P(Ham), u64p, u64p, f64p, C.c_int, f64p]
+        L.orc_shift_update.restype = C.c_double
+        L.orc_shift_update.argtypes = [C.c_double] * 7
+        L.orc_step.restype = C.c_int
+        L.orc_step.argtypes = [P(Params), u64p, f64p, C.c_int64, C.c_double, C.c_int64, u64p,
+                               C.c_double, u64p, f64p, C.c_int64, i64p, P(Stats), C.c_void_p,
+                               C.c_int64, i64p, u64p, f64p, C.c_int64, i64p]
+        L.orc_run.restype = C.c_int
+        L.orc_run.argtypes = [P(Params), u64p, f64p, C.c_int64, C.c_double, C.c_int64, C.c_int64,
+                              u64p, C.c_double, C.c_int64, u64p, f64p, i64p, P(Stats)]
+        L.orc_build_csr.restype = C.c_int
+        L.orc_build_csr.argtypes = [P(Ham), i64p, i64p, f64p]
+        L.orc_lanczos.restype = C.c_int
+        L.orc_lanczos.argtypes = [P(Ham), u64p, C.c_int, f64p, f64p, i32p]
+        L.orc_validate.restype = C.c_int
+        L.orc_validate.argtypes = [P(Ham)]
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+    return rc
+
+
+# --------------------------------------------------------------------------
+# Fock addresses [Sec. 6.1]
+# --------------------------------------------------------------------------
+
+def binom(n, k):
+    return int(lib().orc_binom(n, k))
+
+
+def dimension(M, N):
+    """Hilbert dimension C(N+M-1, N) [Sec. 2]."""
+    return int(lib().orc_dimension(M, N))
+
+
+def encode(occ):
+    """Occupations -> (word0, word1) of the unary bitstring [Sec. 6.1]."""
+    o = np.ascontiguousarray(occ, dtype=np.int32)
+    w = np.zeros(2, np.uint64)
+    nb = lib().orc_encode(_p(o, C.c_int32), len(o), _p(w, C.c_uint64))
+    if nb < 0:
+        raise ValueError("address does not fit 128 bits")
+    return int(w[0]), int(w[1])
+
+
+def encode_many(occs):
+    occs = np.asarray(occs, dtype=np.int32)
+    out = np.zeros((len(occs), 2), np.uint64)
+    for i, o in enumerate(occs):
+        out[i] = encode(o)
+    return out
+
+
+def decode(words, M, N):
+    w = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    occ = np.zeros(M, np.int32)
+    lib().orc_decode(_p(w, C.c_uint64), M, N, _p(occ, C.c_int32))
+    return occ
+
+
+def bitstring(occ):
+    """The paper's printed form: N+M-1 bits, most significant first."""
+    occ = list(occ)
+    nb = sum(occ) + len(occ) - 1
+    w0, w1 = encode(occ)
+    v = w0 | (w1 << 64)
+    return format(v, "b").zfill(nb)
+
+
+def rank(words, M, N):
+    w = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    return int(lib().orc_rank(_p(w, C.c_uint64), M, N))
+
+
+def unrank(r, M, N):
+    w = np.zeros(2, np.uint64)
+    lib().orc_unrank(r, M, N, _p(w, C.c_uint64))
+    return int(w[0]), int(w[1])
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+# --------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key):
+    c = np.asarray(ctr, np.uint32)
+    k = np.asarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(o, C.c_uint32))
+    return [int(x) for x in o]
+
+
+def draw(seed, words, step, tag, block):
+    a = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    o = np.zeros(4, np.uint32)
+    lib().orc_draw(seed, _p(a, C.c_uint64), step, tag, block, _p(o, C.c_uint32))
+    return [int(x) for x in o]
+
+
+def det_log(x):
+    return float(lib().orc_det_log(x))
+
+
+def fsum(xs):
+    x = np.ascontiguousarray(xs, dtype=np.float64)
+    return float(lib().orc_fsum(_p(x, C.c_double), len(x)))
+
+
+def shift_update(S, N1, N0, Nt, zeta, xi, dtau):
+    return float(lib().orc_shift_update(S, N1, N0, Nt, zeta, xi, dtau))
+
+
+# --------------------------------------------------------------------------
+# Hamiltonians [Sec. 6.2]
+# --------------------------------------------------------------------------
+
+def ham(model, M, N, t=1.0, u=1.0):
+    return Ham(model, M, N, 0, float(t), float(u))
+
+
+def column(h, words, cap=1 << 16):
+    """(diagonal, dests[m,2], values[m]) in canonical enumeration order."""
+    a = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    dest = np.zeros((cap, 2), np.uint64)
+    vals = np.zeros(cap, np.float64)
+    diag = C.c_double(0.0)
+    m = _check(lib().orc_column(C.byref(h), _p(a, C.c_uint64), _p(dest, C.c_uint64),
+                                _p(vals, C.c_double), cap, C.byref(diag)), "column")
+    return diag.value, dest[:m].copy(), vals[:m].copy()
+
+
+def validate(h):
+    return lib().orc_validate(C.byref(h)) == 0
+
+
+# --------------------------------------------------------------------------
+# FCIQMC [Sec. 3]
+# --------------------------------------------------------------------------
+
+def params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target=1000.0, zeta=0.08, xi=None,
+           theta=1.0, t_rel=1.0, seed=0):
+    if xi is None:
+        xi = zeta * zeta / 4.0
+    return Params(ham(model, M, N, t, u), dtau, target, zeta, xi, theta, t_rel, seed)
+
+
+def _addr2(addrs):
+    a = np.zeros((len(addrs), 2), np.uint64)
+    if len(addrs):
+        arr = np.asarray(addrs, dtype=np.uint64)
+        if arr.ndim == 1:
+            a[:, 0] = arr
+        else:
+            a[:, :arr.shape[1]] = arr
+    return np.ascontiguousarray(a)
+
+
+def step(P, addrs, vals, shift, step_index, ref, yref, cap=None, events=False, merged=False):
+    """One step c^(n) -> c^(n+1); returns dict with table, stats, dumps."""
+    a = _addr2(addrs)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    n = len(v)
+    if cap is None:
+        cap = max(16, 64 * (n + int(np.abs(v).sum()) + 16))
+    oa = np.zeros((cap, 2), np.uint64)
+    ov = np.zeros(cap, np.float64)
+    on = C.c_int64(0)
+    st = Stats()
+    r = np.asarray([int(ref[0]), int(ref[1])], np.uint64)
+    ev = np.zeros(cap if events else 0, EVENT_DTYPE)
+    evn = C.c_int64(0)
+    mga = np.zeros((cap if merged else 0, 2), np.uint64)
+    mgv = np.zeros(cap if merged else 0, np.float64)
+    mgn = C.c_int64(0)
+    rc = lib().orc_step(C.byref(P), _p(a, C.c_uint64), _p(v, C.c_double), n, shift, step_index,
+                        _p(r, C.c_uint64), yref, _p(oa, C.c_uint64), _p(ov, C.c_double), cap,
+                        C.byref(on), C.byref(st),
+                        ev.ctypes.data if events else None, len(ev), C.byref(evn),
+                        _p(mga, C.c_uint64) if merged else None,
+                        _p(mgv, C.c_double) if merged else None, len(mgv), C.byref(mgn))
+    _check(rc, "step")
+    out = dict(addr=oa[:on.value].copy(), val=ov[:on.value].copy(),
+               stats={f: getattr(st, f) for f in STATS_FIELDS})
+    if events:
+        if evn.value > len(ev):
+            raise RuntimeError("event capacity exceeded")
+        out["events"] = ev[:evn.value].copy()
+    if merged:
+        out["merged_addr"] = mga[:mgn.value].copy()
+        out["merged_val"] = mgv[:mgn.value].copy()
+    return out
+
+
+def run(P, addrs, vals, shift, first_step, nsteps, ref, yref, cap=None):
+    """Repeated steps; returns (stats structured array, final addr, final val)."""
+    a = _addr2(addrs)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    if cap is None:
+        cap = 1 << 22
+    oa = np.zeros((cap, 2), np.uint64)
+    ov = np.zeros(cap, np.float64)
+    on = C.c_int64(0)
+    stats = (Stats * nsteps)()
+    r = np.asarray([int(ref[0]), int(ref[1])], np.uint64)
+    rc = lib().orc_run(C.byref(P), _p(a, C.c_uint64), _p(v, C.c_double), len(v), shift,
+                       first_step, nsteps, _p(r, C.c_uint64), yref, cap, _p(oa, C.c_uint64),
+                       _p(ov, C.c_double), C.byref(on), stats)
+    _check(rc, "run")
+    dt = np.dtype([(f, np.int64 if f in ("step", "len", "exact_steps", "inexact_steps", "spawns")
+                    else np.float64) for f in STATS_FIELDS])
+    arr = np.zeros(nsteps, dt)
+    for k in range(nsteps):
+        for f in STATS_FIELDS:
+            arr[f][k] = getattr(stats[k], f)
+    return arr, oa[:on.value].copy(), ov[:on.value].copy()
+
+
+# --------------------------------------------------------------------------
+# Exact diagonalisation [Sec. 5]
+# --------------------------------------------------------------------------
+
+def csr_matrix(h):
+    """H as scipy.sparse CSR over the ranked basis (column j -> rows)."""
+    import scipy.sparse as sp
+    D = dimension(h.M, h.N)
+    indptr = np.zeros(D + 1, np.int64)
+    _check(lib().orc_build_csr(C.byref(h), _p(indptr, C.c_int64), None, None), "csr count")
+    nnz = int(indptr[-1])
+    ind = np.zeros(nnz, np.int64)
+    dat = np.zeros(nnz, np.float64)
+    _check(lib().orc_build_csr(C.byref(h), _p(indptr, C.c_int64), _p(ind, C.c_int64),
+                               _p(dat, C.c_double)), "csr fill")
+    # column j stores (row indices, values): this is CSC of H, i.e. CSR of H^T.
+    m = sp.csc_matrix((dat, ind, indptr), shape=(D, D))
+    return m.tocsr()
+
+
+def dense_matrix(h):
+    return csr_matrix(h).toarray()
+
+
+def lanczos(h, start, kmax=200):
+    """Lowest Ritz value from plain matrix-free Lanczos started at `start`."""
+    from scipy.linalg import eigh_tridiagonal
+    s = np.asarray([int(start[0]), int(start[1])], np.uint64)
+    al = np.zeros(kmax)
+    be = np.zeros(kmax)
+    k = C.c_int32(0)
+    _check(lib().orc_lanczos(C.byref(h), _p(s, C.c_uint64), kmax, _p(al, C.c_double),
+                             _p(be, C.c_double), C.byref(k)), "lanczos")
+    k = k.value
+    w = eigh_tridiagonal(al[:k], be[:k - 1], eigvals_only=True)
+    return np.sort(w)
+
+
+def eigs_sparse(h, k=2):
+    from scipy.sparse.linalg import eigsh
+    m = csr_matrix(h)
+    w = eigsh(m, k=k, which="SA", return_eigenvectors=False, tol=1e-12)
+    return np.sort(w)
+
+
+def start_address(model, M, N):
+    """Starting address: the uniform (near_uniform) state in real space; the
+    k = 0 condensate in momentum space (reading for the momentum model)."""
+    if model == MOM1D:
+        occ = [0] * M
+        occ[0] = N
+    else:
+        occ = [N // M + (1 if j < N % M else 0) for j in range(M)]
+    return encode(occ)
