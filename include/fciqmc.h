@@ -1,0 +1,178 @@
+/*
+ * fciqmc.h -- C ABI of the MI355X (gfx950) FCIQMC hot-path library.
+ *
+ * The library advances the FCIQMC projector iteration of the Rimu.jl paper
+ * (arXiv 2601.19505) on one GPU:
+ *
+ *   c^(n+1) = Pi[ (1 + dtau (S^(n) - H~)) c^(n) ]          (Sec. 3.2, Eqs.
+ *             fciqmc-stochastic and stochasticTransitionOperator)
+ *   S^(n+1) = S^(n) - (zeta/dtau) ln(N^(n+1)/N^(n))
+ *                   - (xi/dtau)  ln(N^(n+1)/N_t)            (Sec. 3.1, Eq. shift-update)
+ *
+ * for the 1D periodic Bose-Hubbard Hamiltonian in real space (Sec. 2, Eq.
+ * bose-hubbard-hamiltonian) or in momentum space (HubbardMom1D, Sec. 6.3),
+ * acting matrix-free on bit-packed bosonic Fock addresses (Sec. 6.1).  One
+ * step is: per occupied address, stochastic or exact off-diagonal spawning
+ * (matrix compression, Eq. column-compression; exact columns per the
+ * semistochastic threshold of Sec. 7.1) and the diagonal death/cloning;
+ * annihilation by summing all contributions per address (Sec. 3.2); late
+ * stochastic vector compression with threshold theta (Eq. vec-compression,
+ * Sec. 7.1); the shift update and the projected-energy numerator y^T H c and
+ * denominator y^T c for a one-address reference vector y (Sec. 4.2, Eq.
+ * ProjectedEnergy).
+ *
+ * Addresses.  A Fock state |n_1 .. n_M> is its unary bitstring of N+M-1 bits
+ * (Sec. 6.1): n_1 ones in the lowest bits, a zero separator, n_2 ones, ...
+ * It is passed as `addr_words` (W = 1 or 2) little-endian 64-bit words per
+ * address; word 0 holds bits 0..63.  W = 1 requires N+M-1 <= 62, W = 2
+ * requires N+M-1 <= 126.  The results never depend on W.
+ *
+ * Memory.  The caller owns all memory.  Device memory is one workspace of
+ * fq_workspace_size() bytes (any 256-byte aligned device allocation); the
+ * library never allocates or frees device memory (it keeps small host-side
+ * bookkeeping only).  Host arrays passed in are read or written during the
+ * call and not retained.  `stream` is a hipStream_t (NULL = default
+ * stream); every call enqueues its work on that stream and returns after the
+ * work it reports on has completed.
+ *
+ * Errors.  Every function returns an fq_status.  No exception crosses the
+ * ABI.  A failed step (capacity overflow, divergence) leaves the handle at
+ * the last completed step, so the caller can enlarge the workspace (or
+ * re-create with more buckets), set the state again and continue; because
+ * all random numbers are counter-based, the retried step is identical.
+ * fq_last_error() returns a human-readable description of the last failure.
+ *
+ * Determinism.  Given (Hamiltonian, parameters, state, step index, seed) the
+ * result is bit-identical regardless of bucket count, LDS table size,
+ * workgroup size, launch order, or other instances sharing a batch:
+ * random numbers are Philox4x32-10 draws keyed on (seed, step, address,
+ * attempt), and every sum (annihilation, norm, projected energy) is an exact
+ * fixed-point integer sum rounded once to the nearest double.
+ */
+#ifndef FCIQMC_H
+#define FCIQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FQ_OK = 0,
+    FQ_EINVAL = -1,     /* invalid argument (parameters, sizes, addresses)      */
+    FQ_ECAPACITY = -2,  /* a table, spawn slab or LDS bucket overflowed         */
+    FQ_EHIP = -3,       /* a HIP runtime call failed                            */
+    FQ_ENOMEM = -4,     /* workspace smaller than fq_workspace_size() / host    */
+    FQ_EBUSY = -5,      /* server: no slot or budget for the request now        */
+    FQ_EDIVERGED = -6,  /* walker number overflowed or became non-finite        */
+    FQ_ENOTFOUND = -7   /* server: unknown request id                           */
+} fq_status;
+
+typedef enum { FQ_REAL1D = 0, FQ_MOM1D = 1 } fq_model;
+
+/* Hamiltonian (Sec. 2 and Sec. 6.2): model, M modes, N bosons, hopping t,
+ * on-site interaction u.  Momentum space requires M >= 3. */
+typedef struct {
+    int32_t model, M, N, reserved;
+    double t, u;
+} fq_hamiltonian;
+
+/* Flags of fq_params.flags */
+#define FQ_FLAG_DUMP_SPAWNS 1   /* record every spawn event (parity testing)      */
+#define FQ_FLAG_DUMP_MERGED 2   /* record every merged pre-compression amplitude  */
+
+/* Algorithm parameters.  dtau: time step (Sec. 3.1); target_walkers: N_t;
+ * zeta, xi: shift damping and forcing (Eq. shift-update; defaults 0.08 and
+ * zeta^2/4 reproduce the paper's printed series); threshold: theta of the
+ * vector compression (default 1); t_rel: semistochastic threshold, a column
+ * is spawned exactly when |c| >= t_rel m (Sec. 7.1); seed: 64-bit seed of
+ * the counter-based generator; addr_words: W. */
+typedef struct {
+    double dtau, target_walkers, zeta, xi, threshold, t_rel;
+    uint64_t seed;
+    int32_t addr_words, flags;
+} fq_params;
+
+/* One row of the per-step time series (Sec. 4, the DataFrame columns):
+ * `step` n, `len` = number of stored addresses of c^(n), `exact_steps` and
+ * `inexact_steps` = parents of c^(n-1) spawned exactly / stochastically,
+ * `spawns` = spawn events of step n, `shift` = S^(n), `norm` = ||c^(n)||_1,
+ * `hproj` = y^T H c^(n), `vproj` = y^T c^(n). */
+typedef struct {
+    int64_t step, len, exact_steps, inexact_steps, spawns;
+    double shift, norm, hproj, vproj;
+} fq_step_stats;
+
+/* Sizes of the device data structures.  table_capacity: largest number of
+ * stored addresses; spawn_capacity: largest number of spawn events per step;
+ * buckets: hash buckets (power of two, 0 = choose); lds_slots: LDS hash slots
+ * per bucket (power of two, 1024..8192, 0 = 4096); block: threads per
+ * workgroup (256, 512 or 1024; 0 = choose). */
+typedef struct {
+    int64_t table_capacity, spawn_capacity;
+    int32_t buckets, lds_slots, block, reserved;
+} fq_layout;
+
+typedef struct fq_handle fq_handle;
+
+/* Bytes of device workspace needed for (h, p, layout); fills the defaults
+ * chosen for zero fields of *layout when `layout_out` is not NULL. */
+int fq_workspace_size(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout,
+                      size_t *bytes, fq_layout *layout_out);
+
+/* Creates a handle on `workspace` (device pointer, >= fq_workspace_size
+ * bytes, owned by the caller and kept alive until fq_destroy).  The device
+ * is the current HIP device. */
+int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout,
+              void *workspace, size_t bytes, fq_handle **out);
+
+/* Sets the state c^(step) = {(addrs[i], vals[i])} (host arrays, n entries,
+ * n * W words, distinct addresses with N bosons in M modes), the shift
+ * S^(step), and the reference vector y = ref_val e_ref for the projected
+ * energy (Sec. 4.2; the paper's default is y = c^(0) = 10 e_start). */
+int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_t n, double shift,
+                 int64_t step, const uint64_t *ref_addr, double ref_val, void *stream);
+
+/* Advances n_steps steps; stats_out (host, n_steps rows, may be NULL)
+ * receives one row per step.  On error the handle stays at the last
+ * completed step and the rows of completed steps are filled. */
+int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream);
+
+/* Copies the current state to host arrays (capacity `cap` entries): addrs
+ * (n * W words), vals, and the current shift and step.  Order unspecified. */
+int fq_get_state(fq_handle *q, uint64_t *addrs, double *vals, int64_t cap, int64_t *n,
+                 double *shift, int64_t *step, void *stream);
+
+/* Parity support: events of the spawn pass that produced the current slab
+ * (FQ_FLAG_DUMP_SPAWNS) as parent address (W words), attempt, destination
+ * (W words), value; and the merged pre-compression amplitudes of the last
+ * step (FQ_FLAG_DUMP_MERGED) as address (W words), value.  Host arrays. */
+int fq_read_spawn_dump(fq_handle *q, uint64_t *parent, int64_t *attempt, uint64_t *dest,
+                       double *value, int64_t cap, int64_t *n, void *stream);
+int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap, int64_t *n,
+                        void *stream);
+
+/* Total time (ms) and count of the fused step-kernel launches timed with
+ * HIP events on the run stream since the last reset; timing is enabled
+ * while `enable` is non-zero (it adds one event pair per launch). */
+int fq_set_timing(fq_handle *q, int32_t enable);
+int fq_kernel_time(fq_handle *q, double *ms, int64_t *launches, int32_t reset);
+
+/* Current layout (with defaults resolved) and largest LDS load seen. */
+int fq_get_layout(const fq_handle *q, fq_layout *layout);
+
+int fq_destroy(fq_handle *q);
+const char *fq_last_error(const fq_handle *q);
+
+/* Host helper: occupations -> W address words (the encoding of Sec. 6.1). */
+int fq_encode(const int32_t *occ, int32_t M, int32_t W, uint64_t *out);
+
+/* Library version string. */
+const char *fq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

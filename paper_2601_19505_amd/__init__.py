@@ -1,0 +1,269 @@
+"""MI355X-native FCIQMC hot path (Rimu.jl, arXiv 2601.19505), Python binding.
+
+Thin ctypes marshalling over the C ABI of ``include/fciqmc.h``
+(``libfciqmc.so``, built for gfx950).  Every step of the method runs in the
+HIP kernels of that library; PyTorch is used only to allocate the device
+workspace and to supply the current stream.  Importing this package does not
+need a GPU; creating a solver does, and fails loudly if the library is
+missing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfciqmc.so")
+
+REAL1D = 0
+MOM1D = 1
+
+FLAG_DUMP_SPAWNS = 1
+FLAG_DUMP_MERGED = 2
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ENOMEM", -5: "EBUSY",
+          -6: "EDIVERGED", -7: "ENOTFOUND"}
+
+
+class FqError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Hamiltonian(C.Structure):
+    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("reserved", C.c_int32),
+                ("t", C.c_double), ("u", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dtau", C.c_double), ("target_walkers", C.c_double), ("zeta", C.c_double),
+                ("xi", C.c_double), ("threshold", C.c_double), ("t_rel", C.c_double),
+                ("seed", C.c_uint64), ("addr_words", C.c_int32), ("flags", C.c_int32)]
+
+
+class Layout(C.Structure):
+    _fields_ = [("table_capacity", C.c_int64), ("spawn_capacity", C.c_int64),
+                ("buckets", C.c_int32), ("lds_slots", C.c_int32), ("block", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("step", C.c_int64), ("len", C.c_int64), ("exact_steps", C.c_int64),
+                ("inexact_steps", C.c_int64), ("spawns", C.c_int64), ("shift", C.c_double),
+                ("norm", C.c_double), ("hproj", C.c_double), ("vproj", C.c_double)]
+
+
+STATS_DTYPE = np.dtype([("step", np.int64), ("len", np.int64), ("exact_steps", np.int64),
+                        ("inexact_steps", np.int64), ("spawns", np.int64), ("shift", np.float64),
+                        ("norm", np.float64), ("hproj", np.float64), ("vproj", np.float64)])
+assert STATS_DTYPE.itemsize == C.sizeof(StepStats)
+
+_lib = None
+
+
+def lib():
+    """Load libfciqmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2601_19505_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        u64p, f64p, i64p, i32p = P(C.c_uint64), P(C.c_double), P(C.c_int64), P(C.c_int32)
+        sig = {
+            "fq_version": (C.c_char_p, []),
+            "fq_encode": (C.c_int, [i32p, C.c_int32, C.c_int32, u64p]),
+            "fq_workspace_size": (C.c_int, [P(Hamiltonian), P(Params), P(Layout), P(C.c_size_t),
+                                            P(Layout)]),
+            "fq_create": (C.c_int, [P(Hamiltonian), P(Params), P(Layout), vp, C.c_size_t, P(vp)]),
+            "fq_set_state": (C.c_int, [vp, u64p, f64p, C.c_int64, C.c_double, C.c_int64, u64p,
+                                       C.c_double, vp]),
+            "fq_run": (C.c_int, [vp, C.c_int64, vp, vp]),
+            "fq_get_state": (C.c_int, [vp, u64p, f64p, C.c_int64, i64p, f64p, i64p, vp]),
+            "fq_read_spawn_dump": (C.c_int, [vp, u64p, i64p, u64p, f64p, C.c_int64, i64p, vp]),
+            "fq_read_merged_dump": (C.c_int, [vp, u64p, f64p, C.c_int64, i64p, vp]),
+            "fq_set_timing": (C.c_int, [vp, C.c_int32]),
+            "fq_kernel_time": (C.c_int, [vp, f64p, i64p, C.c_int32]),
+            "fq_get_layout": (C.c_int, [vp, P(Layout)]),
+            "fq_destroy": (C.c_int, [vp]),
+            "fq_last_error": (C.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def encode(occ, W=1):
+    """Occupation numbers -> W address words (host helper of the library)."""
+    o = np.ascontiguousarray(occ, dtype=np.int32)
+    out = np.zeros(W, np.uint64)
+    rc = lib().fq_encode(_p(o, C.c_int32), len(o), W, _p(out, C.c_uint64))
+    if rc:
+        raise FqError(rc, "fq_encode")
+    return out
+
+
+def encode_many(occs, W=1):
+    occs = np.asarray(occs, dtype=np.int32)
+    return np.stack([encode(o, W) for o in occs]) if len(occs) else np.zeros((0, W), np.uint64)
+
+
+def workspace_size(ham, params, layout):
+    nb = C.c_size_t(0)
+    lo = Layout()
+    rc = lib().fq_workspace_size(C.byref(ham), C.byref(params), C.byref(layout), C.byref(nb),
+                                 C.byref(lo))
+    if rc:
+        raise FqError(rc, "fq_workspace_size: invalid parameters or layout")
+    return nb.value, lo
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """One FCIQMC instance on the current GPU (plain per-step launches)."""
+
+    def __init__(self, model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08,
+                 xi=None, threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0,
+                 table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the FCIQMC solver needs a GPU")
+        if xi is None:
+            xi = zeta * zeta / 4.0
+        self.ham = Hamiltonian(model, M, N, 0, float(t), float(u))
+        self.params = Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words,
+                             flags)
+        self.W = addr_words
+        nbytes, lay = workspace_size(self.ham, self.params,
+                                     Layout(table_capacity, spawn_capacity, buckets, lds_slots,
+                                            block, 0))
+        self.layout = lay
+        self.nbytes = nbytes
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        rc = lib().fq_create(C.byref(self.ham), C.byref(self.params), C.byref(lay),
+                             C.c_void_p(self.ws.data_ptr()), nbytes, C.byref(h))
+        if rc:
+            raise FqError(rc, "fq_create")
+        self.h = h
+        self.table_capacity = lay.table_capacity
+        self.spawn_capacity = lay.spawn_capacity
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().fq_last_error(self.h)
+            raise FqError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _addr(self, addrs):
+        a = np.asarray(addrs, dtype=np.uint64)
+        if a.ndim == 1:
+            a = a[:, None]
+        if a.shape[1] < self.W:
+            a = np.concatenate([a, np.zeros((len(a), self.W - a.shape[1]), np.uint64)], 1)
+        elif a.shape[1] > self.W:
+            if np.any(a[:, self.W:]):
+                raise ValueError("address does not fit addr_words")
+            a = a[:, :self.W]
+        return np.ascontiguousarray(a)
+
+    def set_state(self, addrs, vals, shift=0.0, step=0, ref=None, yref=10.0):
+        a = self._addr(addrs)
+        v = np.ascontiguousarray(vals, dtype=np.float64)
+        r = self._addr([a[0] if ref is None else ref])[0].copy()
+        self._check(lib().fq_set_state(self.h, _p(a, C.c_uint64), _p(v, C.c_double), len(v),
+                                       float(shift), int(step), _p(r, C.c_uint64), float(yref),
+                                       _stream()), "fq_set_state")
+
+    def run(self, n_steps):
+        out = np.zeros(n_steps, STATS_DTYPE)
+        rc = lib().fq_run(self.h, n_steps, C.c_void_p(out.ctypes.data), _stream())
+        if rc:
+            msg = lib().fq_last_error(self.h)
+            err = FqError(rc, f"fq_run: {msg.decode() if msg else ''}")
+            err.stats = out
+            raise err
+        return out
+
+    def get_state(self, cap=None):
+        if cap is None:
+            cap = self.table_capacity + 1024
+        a = np.zeros((cap, self.W), np.uint64)
+        v = np.zeros(cap, np.float64)
+        n = C.c_int64(0)
+        sh = C.c_double(0)
+        st = C.c_int64(0)
+        self._check(lib().fq_get_state(self.h, _p(a, C.c_uint64), _p(v, C.c_double), cap,
+                                       C.byref(n), C.byref(sh), C.byref(st), _stream()),
+                    "fq_get_state")
+        return a[:n.value].copy(), v[:n.value].copy(), sh.value, st.value
+
+    def spawn_dump(self, cap=None):
+        cap = cap or (self.spawn_capacity + self.table_capacity)
+        par = np.zeros((cap, self.W), np.uint64)
+        att = np.zeros(cap, np.int64)
+        dst = np.zeros((cap, self.W), np.uint64)
+        val = np.zeros(cap, np.float64)
+        n = C.c_int64(0)
+        self._check(lib().fq_read_spawn_dump(self.h, _p(par, C.c_uint64), _p(att, C.c_int64),
+                                             _p(dst, C.c_uint64), _p(val, C.c_double), cap,
+                                             C.byref(n), _stream()), "fq_read_spawn_dump")
+        k = n.value
+        return par[:k].copy(), att[:k].copy(), dst[:k].copy(), val[:k].copy()
+
+    def merged_dump(self, cap=None):
+        cap = cap or (self.spawn_capacity + self.table_capacity)
+        a = np.zeros((cap, self.W), np.uint64)
+        v = np.zeros(cap, np.float64)
+        n = C.c_int64(0)
+        self._check(lib().fq_read_merged_dump(self.h, _p(a, C.c_uint64), _p(v, C.c_double), cap,
+                                              C.byref(n), _stream()), "fq_read_merged_dump")
+        return a[:n.value].copy(), v[:n.value].copy()
+
+    def set_timing(self, on=True):
+        self._check(lib().fq_set_timing(self.h, 1 if on else 0), "fq_set_timing")
+
+    def kernel_time(self, reset=False):
+        ms = C.c_double(0)
+        n = C.c_int64(0)
+        self._check(lib().fq_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0),
+                    "fq_kernel_time")
+        return ms.value, n.value
+
+    def get_layout(self):
+        lo = Layout()
+        self._check(lib().fq_get_layout(self.h, C.byref(lo)), "fq_get_layout")
+        return lo
+
+
+def start_address(model, M, N, W=1):
+    """Default starting address: the uniform state in real space, the k = 0
+    condensate in momentum space."""
+    if model == MOM1D:
+        occ = [N] + [0] * (M - 1)
+    else:
+        occ = [N // M + (1 if j < N % M else 0) for j in range(M)]
+    return encode(occ, W)

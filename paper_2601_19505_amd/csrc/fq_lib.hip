@@ -1,0 +1,781 @@
+// fq_lib.hip -- kernels and host runtime behind the C ABI of include/fciqmc.h.
+//
+// One plain step = one launch of k_step over the B buckets of an instance
+// (grid = B workgroups, one bucket each); the last workgroup to finish
+// performs the shift update, so there is no second launch and no host
+// synchronisation between steps.  The host only synchronises at the end of a
+// chunk of steps to copy the statistics rows and check the error word.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fciqmc.h"
+#include "fq_step.hpp"
+
+using namespace fq;
+
+// ------------------------------------------------------------------ kernels
+
+template <int W, int MODEL, int BS>
+__global__ __launch_bounds__(BS) void k_step(const Inst *I, int mode)
+{
+    extern __shared__ __align__(16) char smem[];
+    process_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, mode, smem);
+}
+
+// insert host-staged entries into table[parity] and accumulate the norm
+template <int W>
+__global__ __launch_bounds__(256) void k_insert(const Inst *Ip, const u64 *sa, const double *sv, i64 n)
+{
+    const Inst &I = *Ip;
+    Ctrl *ctrl = I.ctrl;
+    const int p = ctrl->parity;
+    __shared__ u64 acc[2];
+    if (threadIdx.x == 0) acc[0] = acc[1] = 0;
+    __syncthreads();
+    u64 nlo = 0, nhi = 0;
+    for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        u64 a0 = sa[i * W], a1 = W == 2 ? sa[i * W + 1] : 0;
+        double v = sv[i];
+        u32 b = bucket_of(addr_hash(AddrOf<W>::make(a0, a1)), I.log2B);
+        int pos = atomicAdd(&I.tab_n[p][b], 1);
+        if (pos >= I.cap_t) { set_error(ctrl, FQE_CAP_TABLE, (int)b); continue; }
+        i64 o = (i64)b * I.cap_t + pos;
+        I.tab_a[p][0][o] = a0;
+        if (W == 2) I.tab_a[p][1][o] = a1;
+        I.tab_v[p][o] = v;
+        u64 lo, hi;
+        int ovf = 0;
+        to_fixed(fabs(v), lo, hi, ovf);
+        if (ovf) set_error(ctrl, FQE_DIVERGED, (int)b);
+        add128(nlo, nhi, lo, hi);
+    }
+    if (nlo | nhi) lds_acc128(&acc[0], &acc[1], nlo, nhi);
+    __syncthreads();
+    if (threadIdx.x == 0 && (acc[0] | acc[1])) glb_acc128(ctrl->acc_norm, acc[0], acc[1]);
+}
+
+// finish set_state: norm of the inserted vector -> ctrl->norm
+__global__ void k_take_norm(const Inst *Ip)
+{
+    Ctrl *c = Ip->ctrl;
+    c->norm = from_fixed(c->acc_norm[0], c->acc_norm[1]);
+    c->acc_norm[0] = c->acc_norm[1] = 0;
+}
+
+// column of the reference address: entry 0 is the diagonal, then the
+// off-diagonal entries; bucket of every destination
+template <int W, int MODEL>
+__global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *ob, int *on, int cap)
+{
+    const Inst &I = *Ip;
+    typedef typename AddrOf<W>::T T;
+    __shared__ unsigned char row[MOM_ROW];
+    if (threadIdx.x != 0) return;
+    T a = AddrOf<W>::make(r0, r1);
+    int k = 0;
+    double hd;
+    i64 m;
+    MomRow R = mom_row(row);
+    if (MODEL == 0) {
+        hd = real_diag(I.mc, a);
+        m = 2 * popc(run_starts(a));
+    } else {
+        mom_decode(I.mc, a, R);
+        hd = mom_diag(I.mc, R);
+        m = mom_m(R, I.mc.M);
+    }
+    if (m + 1 > cap) { *on = -1; return; }
+    oa[0] = r0;
+    oa[1] = r1;
+    oh[0] = hd;
+    ob[0] = (int)bucket_of(addr_hash(a), I.log2B);
+    k = 1;
+    T st = run_starts(a);
+    int o = popc(st);
+    for (i64 e = 0; e < m; e++) {
+        double h;
+        T d;
+        if (MODEL == 0) {
+            d = real_entry(I.mc, a, st, o, (int)e, h);
+        } else {
+            int pp, qq, di;
+            mom_entry(R, I.mc.M, e, pp, qq, di);
+            d = mom_move(I.mc, a, R, pp, qq, di, h);
+        }
+        oa[2 * k] = word0(d);
+        oa[2 * k + 1] = word1(d);
+        oh[k] = h;
+        ob[k] = (int)bucket_of(addr_hash(d), I.log2B);
+        k++;
+    }
+    *on = k;
+}
+
+// copy table[parity] into contiguous arrays
+template <int W>
+__global__ __launch_bounds__(256) void k_pack(const Inst *Ip, u64 *oa, double *ov, unsigned long long *cnt)
+{
+    const Inst &I = *Ip;
+    const int p = I.ctrl->parity;
+    for (int b = blockIdx.x; b < I.B; b += gridDim.x) {
+        const int nb = I.tab_n[p][b];
+        __shared__ unsigned long long base;
+        if (threadIdx.x == 0) base = nb ? atomicAdd(cnt, (unsigned long long)nb) : 0ull;
+        __syncthreads();
+        for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+            i64 s = (i64)b * I.cap_t + i, d = (i64)base + i;
+            oa[d * W] = I.tab_a[p][0][s];
+            if (W == 2) oa[d * W + 1] = I.tab_a[p][1][s];
+            ov[d] = I.tab_v[p][s];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_set_i64(i64 *p, i64 v) { *p = v; }
+
+// ------------------------------------------------------------------ host side
+
+namespace {
+
+constexpr i64 RING = 4096;
+constexpr int REFCAP = 1 << 15;
+
+typedef void (*StepFn)(const Inst *, int);
+
+struct KernelSet {
+    const void *step;
+    int bs;
+};
+
+template <int W, int MODEL>
+const void *pick_step(int bs)
+{
+    switch (bs) {
+    case 256: return (const void *)k_step<W, MODEL, 256>;
+    case 512: return (const void *)k_step<W, MODEL, 512>;
+    default: return (const void *)k_step<W, MODEL, 1024>;
+    }
+}
+
+const void *step_kernel(int W, int model, int bs)
+{
+    if (W == 1) return model == 0 ? pick_step<1, 0>(bs) : pick_step<1, 1>(bs);
+    return model == 0 ? pick_step<2, 0>(bs) : pick_step<2, 1>(bs);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int ilog2(i64 x)
+{
+    int r = 0;
+    while (((i64)1 << r) < x) r++;
+    return r;
+}
+
+size_t rec_bytes(int W) { return W == 1 ? 16 : 24; }
+
+size_t lds_bytes(int W, int model, int slots, int bs)
+{
+    size_t per = 8 + (W == 2 ? 8 : 0) + 8 + 8 + (W == 2 ? 4 : 0);
+    size_t b = (size_t)slots * per + 64 * 8;
+    if (model == 1) b += (size_t)bs * MOM_ROW;
+    return b;
+}
+
+constexpr size_t LDS_MAX = 160 * 1024;
+
+struct Resolved {
+    int W, nb, B, log2B, slots, block;
+    i64 cap_t, cap_s, dump_cap;
+    size_t off_ctrl, off_inst, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
+        off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
+        off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, total;
+    int nsq;
+};
+
+int validate(const fq_hamiltonian *h, const fq_params *p, std::string &err)
+{
+    if (!h || !p) { err = "null argument"; return FQ_EINVAL; }
+    if (h->model != FQ_REAL1D && h->model != FQ_MOM1D) { err = "unknown model"; return FQ_EINVAL; }
+    if (h->M < 2 || h->N < 1) { err = "need M >= 2 and N >= 1"; return FQ_EINVAL; }
+    if (h->model == FQ_MOM1D && (h->M < 3 || h->M > MOM_MAXM)) { err = "momentum model needs 3 <= M <= 32"; return FQ_EINVAL; }
+    if (p->addr_words != 1 && p->addr_words != 2) { err = "addr_words must be 1 or 2"; return FQ_EINVAL; }
+    int nb = h->N + h->M - 1;
+    if (nb > (p->addr_words == 1 ? 62 : 126)) { err = "N+M-1 too large for addr_words"; return FQ_EINVAL; }
+    if (!(p->dtau > 0) || !(p->target_walkers > 0) || !(p->threshold > 0) || !(p->t_rel >= 0) ||
+        !(p->zeta >= 0) || !(p->xi >= 0) || !std::isfinite(p->dtau)) {
+        err = "dtau, target_walkers, threshold must be > 0; t_rel, zeta, xi >= 0";
+        return FQ_EINVAL;
+    }
+    if (!std::isfinite(h->t) || !std::isfinite(h->u)) { err = "t and u must be finite"; return FQ_EINVAL; }
+    return FQ_OK;
+}
+
+int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, Resolved &R, fq_layout &lout,
+            std::string &err)
+{
+    int rc = validate(h, p, err);
+    if (rc) return rc;
+    if (!lin || lin->table_capacity < 1 || lin->spawn_capacity < 1) {
+        err = "layout capacities must be >= 1";
+        return FQ_EINVAL;
+    }
+    fq_layout L = *lin;
+    L.spawn_capacity = std::max(L.spawn_capacity, L.table_capacity);
+    R.W = p->addr_words;
+    R.nb = h->N + h->M - 1;
+    if (L.lds_slots == 0) L.lds_slots = 4096;
+    if (L.lds_slots < 1024 || L.lds_slots > 8192 || (L.lds_slots & (L.lds_slots - 1))) {
+        err = "lds_slots must be a power of two in [1024, 8192]";
+        return FQ_EINVAL;
+    }
+    if (L.block == 0) L.block = h->model == FQ_MOM1D ? 512 : 1024;
+    if (L.block != 256 && L.block != 512 && L.block != 1024) { err = "block must be 256, 512 or 1024"; return FQ_EINVAL; }
+    if (L.lds_slots > 8 * L.block) { err = "lds_slots must be <= 8 * block"; return FQ_EINVAL; }
+    if (lds_bytes(R.W, h->model, L.lds_slots, L.block) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
+    if (L.buckets == 0) {
+        double uniq = (double)L.table_capacity + 0.25 * (double)L.spawn_capacity;
+        i64 b = (i64)std::ceil(uniq / (0.55 * L.lds_slots));
+        L.buckets = (int)((i64)1 << ilog2(std::max<i64>(b, 1)));
+    }
+    if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > (1 << 22)) {
+        err = "buckets must be a power of two <= 2^22";
+        return FQ_EINVAL;
+    }
+    R.B = L.buckets;
+    R.log2B = ilog2(R.B);
+    R.slots = L.lds_slots;
+    R.block = L.block;
+    auto cap = [](double mean) {
+        double c = mean + 8.0 * std::sqrt(mean) + 64.0;
+        return (i64)std::ceil(c);
+    };
+    R.cap_t = std::min<i64>(cap((double)L.table_capacity / R.B), R.slots);
+    R.cap_s = cap((double)L.spawn_capacity / R.B);
+    R.dump_cap = (p->flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) ? L.spawn_capacity + L.table_capacity : 0;
+    R.nsq = (h->N + 2) * (h->N + 2) + 8;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    R.off_ctrl = take(sizeof(Ctrl));
+    R.off_inst = take(sizeof(Inst));
+    R.off_sq = take(sizeof(double) * R.nsq);
+    R.off_eps = take(sizeof(double) * MOM_MAXM);
+    R.off_ref_a = take(sizeof(u64) * 2 * REFCAP);
+    R.off_ref_h = take(sizeof(double) * REFCAP);
+    R.off_ref_b = take(sizeof(int) * REFCAP);
+    R.off_ref_off = take(sizeof(int) * (R.B + 1));
+    R.off_ref_tmp = take((sizeof(u64) * 2 + sizeof(double) + sizeof(int)) * REFCAP + 64);
+    R.off_ring = take(sizeof(StepStats) * RING);
+    const i64 tn = (i64)R.B * R.cap_t;
+    for (int q = 0; q < 2; q++) {
+        R.off_tab_a[q][0] = take(sizeof(u64) * tn);
+        R.off_tab_a[q][1] = R.W == 2 ? take(sizeof(u64) * tn) : 0;
+        R.off_tab_v[q] = take(sizeof(double) * tn);
+        R.off_tab_n[q] = take(sizeof(int) * R.B);
+        R.off_slab[q] = take(rec_bytes(R.W) * (size_t)R.B * R.cap_s);
+        R.off_slab_n[q] = take(sizeof(int) * R.B);
+    }
+    const i64 dc = std::max<i64>(R.dump_cap, 1);
+    R.off_dsp_parent = take(sizeof(u64) * R.W * dc);
+    R.off_dsp_attempt = take(sizeof(i64) * dc);
+    R.off_dsp_dest = take(sizeof(u64) * R.W * dc);
+    R.off_dsp_val = take(sizeof(double) * dc);
+    R.off_dmg_addr = take(sizeof(u64) * R.W * dc);
+    R.off_dmg_val = take(sizeof(double) * dc);
+    R.total = o;
+    lout = L;
+    return FQ_OK;
+}
+
+}  // namespace
+
+struct fq_handle {
+    fq_hamiltonian h;
+    fq_params p;
+    fq_layout L;
+    Resolved R;
+    char *ws;
+    Inst inst;      // host copy
+    Inst *d_inst;
+    Ctrl *d_ctrl;
+    int have_state;
+    i64 step;
+    int parity;
+    std::string err;
+    int timing;
+    double time_ms;
+    i64 launches;
+    std::vector<hipEvent_t> ev;
+    std::vector<StepStats> ring_host;
+    std::vector<int> ref_bucket_host;
+};
+
+static int hip_fail(fq_handle *q, hipError_t e, const char *what)
+{
+    if (q) q->err = std::string(what) + ": " + hipGetErrorString(e);
+    return FQ_EHIP;
+}
+
+#define HIPCHK(q, call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(q, e_, #call); \
+    } while (0)
+
+static const char *fqe_name(int e)
+{
+    switch (e) {
+    case FQE_CAP_TABLE: return "table bucket capacity exceeded";
+    case FQE_CAP_SLAB: return "spawn slab capacity exceeded";
+    case FQE_CAP_LDS: return "LDS hash of a bucket is full (use more buckets or lds_slots)";
+    case FQE_DIVERGED: return "walker number diverged or became non-finite";
+    case FQE_ATTEMPTS: return "more than 2^30 spawn attempts from one address";
+    case FQE_BARRIER: return "grid barrier timed out";
+    default: return "unknown device error";
+    }
+}
+
+static int fqe_status(int e)
+{
+    switch (e) {
+    case FQE_DIVERGED: return FQ_EDIVERGED;
+    case FQE_ATTEMPTS: return FQ_EINVAL;
+    case FQE_BARRIER: return FQ_EHIP;
+    default: return FQ_ECAPACITY;
+    }
+}
+
+extern "C" {
+
+const char *fq_version(void) { return "fciqmc-mi355x 0.1 (gfx950)"; }
+
+int fq_encode(const int32_t *occ, int32_t M, int32_t W, uint64_t *out)
+{
+    if (!occ || !out || M < 1 || (W != 1 && W != 2)) return FQ_EINVAL;
+    uint64_t w[2] = {0, 0};
+    int pos = 0;
+    for (int j = 0; j < M; j++) {
+        if (occ[j] < 0) return FQ_EINVAL;
+        for (int r = 0; r < occ[j]; r++) {
+            if (pos >= 64 * W) return FQ_EINVAL;
+            w[pos >> 6] |= 1ull << (pos & 63);
+            pos++;
+        }
+        if (j < M - 1) pos++;
+    }
+    if (pos > 64 * W) return FQ_EINVAL;
+    for (int i = 0; i < W; i++) out[i] = w[i];
+    return FQ_OK;
+}
+
+int fq_workspace_size(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout, size_t *bytes,
+                      fq_layout *layout_out)
+{
+    Resolved R;
+    fq_layout L;
+    std::string err;
+    int rc = resolve(h, p, layout, R, L, err);
+    if (rc) return rc;
+    if (bytes) *bytes = R.total;
+    if (layout_out) *layout_out = L;
+    return FQ_OK;
+}
+
+int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout, void *workspace, size_t bytes,
+              fq_handle **out)
+{
+    if (!out) return FQ_EINVAL;
+    *out = nullptr;
+    fq_handle *q = new (std::nothrow) fq_handle();
+    if (!q) return FQ_ENOMEM;
+    int rc = resolve(h, p, layout, q->R, q->L, q->err);
+    if (rc) { delete q; return rc; }
+    if (!workspace || bytes < q->R.total || ((uintptr_t)workspace & 255)) {
+        delete q;
+        return workspace ? FQ_ENOMEM : FQ_EINVAL;
+    }
+    q->h = *h;
+    q->p = *p;
+    q->ws = (char *)workspace;
+    const Resolved &R = q->R;
+    Inst &I = q->inst;
+    memset(&I, 0, sizeof I);
+    I.mc.M = h->M;
+    I.mc.N = h->N;
+    I.mc.nb = R.nb;
+    I.mc.t = h->t;
+    I.mc.u = h->u;
+    I.mc.coef = h->u / (2.0 * (double)h->M);
+    I.mc.sq = (const double *)(q->ws + R.off_sq);
+    I.mc.eps = (const double *)(q->ws + R.off_eps);
+    I.model = h->model;
+    I.W = R.W;
+    I.dtau = p->dtau;
+    I.target = p->target_walkers;
+    I.zeta = p->zeta;
+    I.xi = p->xi;
+    I.theta = p->threshold;
+    I.t_rel = p->t_rel;
+    I.seed = p->seed;
+    I.log2B = R.log2B;
+    I.B = R.B;
+    I.slots = R.slots;
+    I.flags = p->flags;
+    I.cap_t = R.cap_t;
+    I.cap_s = R.cap_s;
+    for (int k = 0; k < 2; k++) {
+        I.tab_a[k][0] = (u64 *)(q->ws + R.off_tab_a[k][0]);
+        I.tab_a[k][1] = R.W == 2 ? (u64 *)(q->ws + R.off_tab_a[k][1]) : nullptr;
+        I.tab_v[k] = (double *)(q->ws + R.off_tab_v[k]);
+        I.tab_n[k] = (int *)(q->ws + R.off_tab_n[k]);
+        I.slab[k] = q->ws + R.off_slab[k];
+        I.slab_n[k] = (int *)(q->ws + R.off_slab_n[k]);
+    }
+    I.ref_a[0] = (u64 *)(q->ws + R.off_ref_a);
+    I.ref_a[1] = I.ref_a[0] + REFCAP;
+    I.ref_h = (double *)(q->ws + R.off_ref_h);
+    I.ref_off = (int *)(q->ws + R.off_ref_off);
+    I.ctrl = (Ctrl *)(q->ws + R.off_ctrl);
+    I.ring = (StepStats *)(q->ws + R.off_ring);
+    I.ring_cap = RING;
+    I.dsp_parent = (u64 *)(q->ws + R.off_dsp_parent);
+    I.dsp_attempt = (i64 *)(q->ws + R.off_dsp_attempt);
+    I.dsp_dest = (u64 *)(q->ws + R.off_dsp_dest);
+    I.dsp_val = (double *)(q->ws + R.off_dsp_val);
+    I.dmg_addr = (u64 *)(q->ws + R.off_dmg_addr);
+    I.dmg_val = (double *)(q->ws + R.off_dmg_val);
+    I.dump_cap = R.dump_cap;
+    q->d_inst = (Inst *)(q->ws + R.off_inst);
+    q->d_ctrl = I.ctrl;
+    // host tables: correctly rounded square roots and the momentum dispersion
+    std::vector<double> sq(R.nsq), eps(MOM_MAXM, 0.0);
+    for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
+    for (int j = 0; j < h->M && j < MOM_MAXM; j++)
+        eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
+    HIPCHK(q, hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl)));
+    const void *kf = step_kernel(R.W, h->model, R.block);
+    size_t lb = lds_bytes(R.W, h->model, R.slots, R.block);
+    HIPCHK(q, hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+    q->ring_host.resize(RING);
+    *out = q;
+    return FQ_OK;
+}
+
+int fq_destroy(fq_handle *q)
+{
+    if (!q) return FQ_EINVAL;
+    for (auto e : q->ev) (void)hipEventDestroy(e);
+    delete q;
+    return FQ_OK;
+}
+
+const char *fq_last_error(const fq_handle *q) { return q ? q->err.c_str() : "null handle"; }
+
+int fq_get_layout(const fq_handle *q, fq_layout *layout)
+{
+    if (!q || !layout) return FQ_EINVAL;
+    *layout = q->L;
+    return FQ_OK;
+}
+
+static int launch_step(fq_handle *q, int mode, hipStream_t s)
+{
+    const Resolved &R = q->R;
+    const void *kf = step_kernel(R.W, q->h.model, R.block);
+    size_t lb = lds_bytes(R.W, q->h.model, R.slots, R.block);
+    void *args[] = {(void *)&q->d_inst, (void *)&mode};
+    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lb, s));
+    return FQ_OK;
+}
+
+static int read_ctrl(fq_handle *q, Ctrl &c, hipStream_t s)
+{
+    HIPCHK(q, hipMemcpyAsync(&c, q->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(q, hipStreamSynchronize(s));
+    return FQ_OK;
+}
+
+static bool valid_address(const uint64_t *a, int W, int M, int N)
+{
+    int nb = N + M - 1, ones = 0;
+    for (int w = 0; w < W; w++) {
+        uint64_t x = a[w];
+        int lo = 64 * w, hi = 64 * (w + 1);
+        if (nb < hi) {
+            int keep = std::max(0, nb - lo);
+            uint64_t mask = keep >= 64 ? ~0ull : ((1ull << keep) - 1);
+            if (x & ~mask) return false;
+        }
+        ones += __builtin_popcountll(x);
+    }
+    return ones == N;
+}
+
+int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_t n, double shift, int64_t step,
+                 const uint64_t *ref_addr, double ref_val, void *stream)
+{
+    if (!q || (n > 0 && (!addrs || !vals)) || n < 1 || !ref_addr || step < 0) {
+        if (q) q->err = "set_state needs n >= 1 entries, a reference address and step >= 0";
+        return FQ_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const Resolved &R = q->R;
+    const int W = R.W;
+    // host-side validation: addresses well formed and distinct, values finite
+    std::vector<std::pair<uint64_t, uint64_t>> keys((size_t)n);
+    for (i64 i = 0; i < n; i++) {
+        if (!valid_address(addrs + i * W, W, q->h.M, q->h.N) || !std::isfinite(vals[i]) || vals[i] == 0.0) {
+            q->err = "invalid address or value at entry " + std::to_string(i);
+            return FQ_EINVAL;
+        }
+        keys[i] = {W == 2 ? addrs[i * W + 1] : 0, addrs[i * W]};
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t i = 1; i < keys.size(); i++)
+        if (keys[i] == keys[i - 1]) { q->err = "duplicate address in state"; return FQ_EINVAL; }
+    if (!valid_address(ref_addr, W, q->h.M, q->h.N)) { q->err = "invalid reference address"; return FQ_EINVAL; }
+    if ((size_t)n * (8 * W + 8) > rec_bytes(W) * (size_t)R.B * R.cap_s || n > (i64)R.B * R.cap_t) {
+        q->err = "state larger than the workspace capacity";
+        return FQ_ECAPACITY;
+    }
+    // fresh control block
+    Ctrl c;
+    memset(&c, 0, sizeof c);
+    c.step = step;
+    c.parity = 0;
+    c.shift = shift;
+    c.ring_base = step + 1;
+    HIPCHK(q, hipMemcpyAsync(q->d_ctrl, &c, sizeof c, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 2; k++) {
+        HIPCHK(q, hipMemsetAsync(q->inst.tab_n[k], 0, sizeof(int) * R.B, s));
+        HIPCHK(q, hipMemsetAsync(q->inst.slab_n[k], 0, sizeof(int) * R.B, s));
+    }
+    // stage entries in the parity-1 slab, insert into table[0]
+    u64 *sa = (u64 *)q->inst.slab[1];
+    double *sv = (double *)(q->inst.slab[1] + sizeof(u64) * W * n);
+    HIPCHK(q, hipMemcpyAsync(sa, addrs, sizeof(u64) * W * n, hipMemcpyHostToDevice, s));
+    HIPCHK(q, hipMemcpyAsync(sv, vals, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    int grid = (int)std::min<i64>((n + 255) / 256, 4096);
+    if (W == 1) hipLaunchKernelGGL(k_insert<1>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, (const u64 *)sa, (const double *)sv, (i64)n);
+    else hipLaunchKernelGGL(k_insert<2>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, (const u64 *)sa, (const double *)sv, (i64)n);
+    HIPCHK(q, hipGetLastError());
+    hipLaunchKernelGGL(k_take_norm, dim3(1), dim3(1), 0, s, (const Inst *)q->d_inst);
+    // reference column (on the device), sorted by bucket on the host
+    u64 *ra = (u64 *)(q->ws + R.off_ref_tmp);
+    double *rh = (double *)(ra + 2 * REFCAP);
+    int *rb = (int *)(rh + REFCAP);
+    int *rn = rb + REFCAP;
+    u64 r0 = ref_addr[0], r1 = W == 2 ? ref_addr[1] : 0;
+#define REFK(W_, M_) hipLaunchKernelGGL((k_ref<W_, M_>), dim3(1), dim3(64), 0, s, (const Inst *)q->d_inst, r0, r1, ra, rh, rb, rn, REFCAP)
+    if (W == 1) { if (q->h.model == 0) REFK(1, 0); else REFK(1, 1); }
+    else { if (q->h.model == 0) REFK(2, 0); else REFK(2, 1); }
+#undef REFK
+    HIPCHK(q, hipGetLastError());
+    int m = 0;
+    HIPCHK(q, hipMemcpyAsync(&m, rn, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(q, hipStreamSynchronize(s));
+    if (m < 1) { q->err = "reference column too long"; return FQ_ECAPACITY; }
+    std::vector<u64> ha(2 * (size_t)m);
+    std::vector<double> hh(m);
+    std::vector<int> hb(m);
+    HIPCHK(q, hipMemcpy(ha.data(), ra, sizeof(u64) * 2 * m, hipMemcpyDeviceToHost));
+    HIPCHK(q, hipMemcpy(hh.data(), rh, sizeof(double) * m, hipMemcpyDeviceToHost));
+    HIPCHK(q, hipMemcpy(hb.data(), rb, sizeof(int) * m, hipMemcpyDeviceToHost));
+    std::vector<int> order(m);
+    for (int i = 0; i < m; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return hb[x] < hb[y]; });
+    std::vector<u64> sa0(m), sa1(m);
+    std::vector<double> sh(m);
+    std::vector<int> off(R.B + 1, 0);
+    int self = -1;
+    for (int k = 0; k < m; k++) {
+        int i = order[k];
+        sa0[k] = ha[2 * i];
+        sa1[k] = ha[2 * i + 1];
+        sh[k] = hh[i];
+        off[hb[i] + 1]++;
+        if (i == 0) self = k;
+    }
+    for (int b = 0; b < R.B; b++) off[b + 1] += off[b];
+    q->inst.ref_n = m;
+    q->inst.ref_self = self;
+    q->inst.yref = ref_val;
+    HIPCHK(q, hipMemcpy(q->inst.ref_a[0], sa0.data(), sizeof(u64) * m, hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->inst.ref_a[1], sa1.data(), sizeof(u64) * m, hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->inst.ref_h, sh.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->inst.ref_off, off.data(), sizeof(int) * (R.B + 1), hipMemcpyHostToDevice));
+    HIPCHK(q, hipMemcpy(q->d_inst, &q->inst, sizeof(Inst), hipMemcpyHostToDevice));
+    // spawns of c^(step) for step+1
+    int rc = launch_step(q, 1, s);
+    if (rc) return rc;
+    Ctrl cc;
+    rc = read_ctrl(q, cc, s);
+    if (rc) return rc;
+    if (cc.error) {
+        q->err = std::string("set_state: ") + fqe_name(cc.error);
+        return fqe_status(cc.error);
+    }
+    q->have_state = 1;
+    q->step = step;
+    q->parity = 0;
+    return FQ_OK;
+}
+
+int fq_set_timing(fq_handle *q, int32_t enable)
+{
+    if (!q) return FQ_EINVAL;
+    q->timing = enable;
+    return FQ_OK;
+}
+
+int fq_kernel_time(fq_handle *q, double *ms, int64_t *launches, int32_t reset)
+{
+    if (!q) return FQ_EINVAL;
+    if (ms) *ms = q->time_ms;
+    if (launches) *launches = q->launches;
+    if (reset) { q->time_ms = 0; q->launches = 0; }
+    return FQ_OK;
+}
+
+int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream)
+{
+    if (!q || n_steps < 0) return FQ_EINVAL;
+    if (!q->have_state) { q->err = "run before set_state"; return FQ_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    if (q->p.flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) {
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->dump_spawn_n, (i64)0);
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->dump_merged_n, (i64)0);
+    }
+    i64 done = 0;
+    while (done < n_steps) {
+        const i64 chunk = std::min<i64>(RING, n_steps - done);
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->ring_base, (i64)(q->step + 1));
+        if (q->timing && (i64)q->ev.size() < 2 * chunk) {
+            size_t old = q->ev.size();
+            q->ev.resize(2 * chunk);
+            for (size_t k = old; k < q->ev.size(); k++) HIPCHK(q, hipEventCreate(&q->ev[k]));
+        }
+        for (i64 k = 0; k < chunk; k++) {
+            if (q->timing) HIPCHK(q, hipEventRecord(q->ev[2 * k], s));
+            int rc = launch_step(q, 0, s);
+            if (rc) return rc;
+            if (q->timing) HIPCHK(q, hipEventRecord(q->ev[2 * k + 1], s));
+        }
+        Ctrl c;
+        int rc = read_ctrl(q, c, s);
+        if (rc) return rc;
+        if (q->timing) {
+            for (i64 k = 0; k < chunk; k++) {
+                float ms = 0;
+                HIPCHK(q, hipEventElapsedTime(&ms, q->ev[2 * k], q->ev[2 * k + 1]));
+                q->time_ms += ms;
+            }
+            q->launches += chunk;
+        }
+        const i64 completed = c.step - q->step;
+        if (completed > 0 && stats_out) {
+            HIPCHK(q, hipMemcpy(stats_out + done, q->inst.ring, sizeof(StepStats) * completed, hipMemcpyDeviceToHost));
+        }
+        done += std::max<i64>(completed, 0);
+        q->step = c.step;
+        q->parity = c.parity;
+        if (c.error) {
+            q->err = std::string(fqe_name(c.error)) + " at step " + std::to_string(c.step + 1) +
+                     (c.err_bucket >= 0 ? " (bucket " + std::to_string(c.err_bucket) + ")" : "");
+            return fqe_status(c.error);
+        }
+        if (completed != chunk) { q->err = "step count mismatch"; return FQ_EHIP; }
+    }
+    return FQ_OK;
+}
+
+int fq_get_state(fq_handle *q, uint64_t *addrs, double *vals, int64_t cap, int64_t *n, double *shift, int64_t *step,
+                 void *stream)
+{
+    if (!q || !n) return FQ_EINVAL;
+    if (!q->have_state) { q->err = "no state"; return FQ_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    const Resolved &R = q->R;
+    const int W = R.W;
+    Ctrl c;
+    int rc = read_ctrl(q, c, s);
+    if (rc) return rc;
+    // pack into the free slab (parity 1 - p)
+    char *buf = q->inst.slab[1 - c.parity];
+    unsigned long long *cnt = (unsigned long long *)buf;
+    u64 *oa = (u64 *)(buf + 256);
+    const i64 total_cap = (i64)R.B * R.cap_t;
+    double *ov = (double *)(oa + (size_t)W * total_cap);
+    if (256 + (8 * W + 8) * (size_t)total_cap > rec_bytes(W) * (size_t)R.B * R.cap_s) {
+        q->err = "slab too small to stage the table";
+        return FQ_ECAPACITY;
+    }
+    HIPCHK(q, hipMemsetAsync(cnt, 0, 8, s));
+    int grid = std::min(R.B, 4096);
+    if (W == 1) hipLaunchKernelGGL(k_pack<1>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, oa, ov, cnt);
+    else hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, oa, ov, cnt);
+    HIPCHK(q, hipGetLastError());
+    unsigned long long tot = 0;
+    HIPCHK(q, hipMemcpyAsync(&tot, cnt, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(q, hipStreamSynchronize(s));
+    *n = (int64_t)tot;
+    if (shift) *shift = c.shift;
+    if (step) *step = c.step;
+    if ((i64)tot > cap) { q->err = "get_state: capacity too small"; return FQ_ECAPACITY; }
+    if (tot) {
+        if (addrs) HIPCHK(q, hipMemcpy(addrs, oa, sizeof(u64) * W * tot, hipMemcpyDeviceToHost));
+        if (vals) HIPCHK(q, hipMemcpy(vals, ov, sizeof(double) * tot, hipMemcpyDeviceToHost));
+    }
+    return FQ_OK;
+}
+
+int fq_read_spawn_dump(fq_handle *q, uint64_t *parent, int64_t *attempt, uint64_t *dest, double *value, int64_t cap,
+                       int64_t *n, void *stream)
+{
+    if (!q || !n) return FQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Ctrl c;
+    int rc = read_ctrl(q, c, s);
+    if (rc) return rc;
+    *n = c.dump_spawn_n;
+    if (c.dump_spawn_n > q->R.dump_cap || c.dump_spawn_n > cap) { q->err = "dump capacity exceeded"; return FQ_ECAPACITY; }
+    i64 k = c.dump_spawn_n;
+    const int W = q->R.W;
+    if (k) {
+        HIPCHK(q, hipMemcpy(parent, q->inst.dsp_parent, sizeof(u64) * W * k, hipMemcpyDeviceToHost));
+        HIPCHK(q, hipMemcpy(attempt, q->inst.dsp_attempt, sizeof(i64) * k, hipMemcpyDeviceToHost));
+        HIPCHK(q, hipMemcpy(dest, q->inst.dsp_dest, sizeof(u64) * W * k, hipMemcpyDeviceToHost));
+        HIPCHK(q, hipMemcpy(value, q->inst.dsp_val, sizeof(double) * k, hipMemcpyDeviceToHost));
+    }
+    return FQ_OK;
+}
+
+int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap, int64_t *n, void *stream)
+{
+    if (!q || !n) return FQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Ctrl c;
+    int rc = read_ctrl(q, c, s);
+    if (rc) return rc;
+    *n = c.dump_merged_n;
+    if (c.dump_merged_n > q->R.dump_cap || c.dump_merged_n > cap) { q->err = "dump capacity exceeded"; return FQ_ECAPACITY; }
+    i64 k = c.dump_merged_n;
+    const int W = q->R.W;
+    if (k) {
+        HIPCHK(q, hipMemcpy(addr, q->inst.dmg_addr, sizeof(u64) * W * k, hipMemcpyDeviceToHost));
+        HIPCHK(q, hipMemcpy(value, q->inst.dmg_val, sizeof(double) * k, hipMemcpyDeviceToHost));
+    }
+    return FQ_OK;
+}
+
+}  // extern "C"

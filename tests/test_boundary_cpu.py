@@ -1,0 +1,79 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol the header declares, and its host helpers agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+import paper_2601_19505_amd as fq
+import synthetic
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(fq_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fq.lib()
+    names = _declared()
+    assert "fq_run" in names and "fq_set_state" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert b"gfx950" in L.fq_version()
+
+
+def test_encode_matches_oracle(orc):
+    rng = np.random.default_rng(3)
+    for M, N, W in [(6, 6, 1), (20, 20, 2), (16, 16, 1), (2, 5, 1), (32, 31, 1), (64, 63, 2)]:
+        occs = synthetic.random_occupations(rng, M, N, 50)
+        for o in occs:
+            g = fq.encode(o, W)
+            w0, w1 = orc.encode(o)
+            assert int(g[0]) == w0
+            assert (int(g[1]) if W == 2 else 0) == w1
+
+
+def test_encode_rejects_overflow():
+    with pytest.raises(fq.FqError):
+        fq.encode([40, 40], 1)
+
+
+def _ws(model=0, M=6, N=6, W=1, **kw):
+    h = fq.Hamiltonian(model, M, N, 0, 1.0, 6.0)
+    p = fq.Params(1e-3, 1e3, 0.08, 0.0016, 1.0, 1.0, 0, W, 0)
+    lay = fq.Layout(kw.get("table", 1000), kw.get("spawn", 4000), kw.get("buckets", 0),
+                    kw.get("slots", 0), kw.get("block", 0), 0)
+    return fq.workspace_size(h, p, lay)
+
+
+def test_workspace_size_and_defaults():
+    n, lay = _ws()
+    assert n > 0 and lay.buckets >= 1 and lay.lds_slots == 4096 and lay.block == 1024
+    n2, lay2 = _ws(table=10_000_000, spawn=40_000_000)
+    assert n2 > n and lay2.buckets & (lay2.buckets - 1) == 0 and lay2.buckets > 1000
+    n3, lay3 = _ws(model=1, M=16, N=16)
+    assert lay3.block == 512
+
+
+@pytest.mark.parametrize("kw", [dict(M=1), dict(model=1, M=2, N=3), dict(M=40, N=30, W=1),
+                                dict(slots=3000), dict(block=128), dict(slots=8192, block=512),
+                                dict(buckets=3)])
+def test_workspace_size_rejects_invalid(kw):
+    with pytest.raises(fq.FqError):
+        _ws(**kw)
+
+
+def test_solver_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        fq.Solver(0, 6, 6)

@@ -1,0 +1,194 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Single steps from the same seeded input state must give bit-identical spawn
+events (parent, attempt, destination, value), bit-identical merged
+pre-compression amplitudes, the identical compressed state and identical
+statistics (the merge, norm and projected-energy sums are exactly rounded on
+both sides, so agreement is bit for bit; the floating-point tolerance of the
+method, 1e-12 relative, is therefore met with margin).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def _fq():
+    import paper_2601_19505_amd as fq
+    return fq
+
+
+def _flush(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2048, block=512,
+             t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0):
+    fq = _fq()
+    _flush(f"[one_step] model={model} M={M} N={N} W={W} n={n_entries} B={buckets} "
+           f"slots={slots} block={block} t_rel={t_rel}")
+    rng = np.random.default_rng(seed)
+    occs = synthetic.random_occupations(rng, M, N, n_entries, momentum_sector=sector)
+    vals = synthetic.random_amplitudes(rng, len(occs), lo=lo, hi=hi)
+    oaddr = np.array([orc.encode(o) for o in occs], dtype=np.uint64)
+    gaddr = fq.encode_many(occs, W)
+    assert np.array_equal(gaddr[:, 0], oaddr[:, 0])
+    ref_o, ref_g = oaddr[0], gaddr[0]
+    P = orc.params(model, M, N, t, u, dtau=dtau, target=1e4, theta=theta, t_rel=t_rel,
+                   seed=seed + 99)
+    o = orc.step(P, oaddr, vals, shift, step + 1, ref_o, 10.0, events=True, merged=True)
+    cap_t = max(4096, 4 * len(occs))
+    s = fq.Solver(model, M, N, t=t, u=u, dtau=dtau, target_walkers=1e4, threshold=theta,
+                  t_rel=t_rel, seed=seed + 99, addr_words=W, flags=3, table_capacity=cap_t,
+                  spawn_capacity=max(8 * len(o["events"]), 65536), buckets=buckets,
+                  lds_slots=slots, block=block)
+    s.set_state(gaddr, vals, shift, step, ref=ref_g, yref=10.0)
+    ev = s.spawn_dump()
+    st = s.run(1)
+    mg = s.merged_dump()
+    ga, gv, gsh, gstep = s.get_state()
+    s.close()
+    return o, ev, st, mg, (ga, gv, gsh, gstep), oaddr
+
+
+def _key2(a):
+    a = np.asarray(a, dtype=np.uint64)
+    if a.ndim == 1 or a.shape[1] == 1:
+        a = a.reshape(-1, 1)
+        return [(0, int(x)) for x in a[:, 0]]
+    return [(int(x[1]), int(x[0])) for x in a]
+
+
+def check_parity(o, ev, st, mg, state, oaddr):
+    # spawn events: identical multisets keyed by (parent, attempt)
+    par, att, dst, val = ev
+    go = {}
+    for p_, a_, d_, v_ in zip(_key2(par), att, _key2(dst), val):
+        go[(p_, int(a_))] = (d_, float(v_).hex())
+    oe = o["events"]
+    oo = {}
+    for e in oe:
+        pk = (int(oaddr[e["parent"]][1]), int(oaddr[e["parent"]][0]))
+        oo[(pk, int(e["attempt"]))] = ((int(e["dest"][1]), int(e["dest"][0])), float(e["value"]).hex())
+    assert len(go) == len(par) == len(oe)
+    assert go == oo
+    # merged amplitudes before compression: bit-identical
+    gm = dict(zip(_key2(mg[0]), (float(x).hex() for x in mg[1])))
+    om = dict(zip(_key2(o["merged_addr"]), (float(x).hex() for x in o["merged_val"])))
+    assert gm == om
+    # compressed state
+    ga, gv, gsh, gstep = state
+    gs = dict(zip(_key2(ga), (float(x).hex() for x in gv)))
+    os_ = dict(zip(_key2(o["addr"]), (float(x).hex() for x in o["val"])))
+    assert gs == os_
+    # statistics row
+    row = st[0]
+    for f in ("step", "len", "exact_steps", "inexact_steps", "spawns"):
+        assert int(row[f]) == int(o["stats"][f]), f
+    for f in ("shift", "norm", "hproj", "vproj"):
+        assert float(row[f]).hex() == float(o["stats"][f]).hex(), (f, row[f], o["stats"][f])
+    assert gsh == row["shift"] and gstep == row["step"]
+
+
+CASES = [
+    # model, M, N, u, dtau, n, seed, W, buckets, slots, block, t_rel
+    (0, 6, 6, 6.0, 1e-3, 200, 1, 1, 4, 1024, 256, 1.0),
+    (0, 8, 5, 2.5, 1e-2, 600, 2, 1, 8, 2048, 512, 0.5),
+    (0, 2, 3, 4.0, 1e-2, 4, 3, 1, 1, 1024, 256, 1.0),
+    (0, 12, 12, 6.0, 1e-3, 3000, 4, 2, 16, 4096, 1024, 1.0),
+    (0, 20, 20, 6.0, 1e-3, 3000, 5, 2, 16, 4096, 512, 1.0),
+    (0, 20, 20, 6.0, 1e-3, 3000, 5, 1, 32, 2048, 1024, 1.0),
+    (1, 5, 4, 3.0, 1e-2, 56, 6, 1, 2, 1024, 256, 1.0),
+    (1, 8, 8, 4.0, 1e-3, 1500, 7, 1, 8, 2048, 512, 1.0),
+    (1, 7, 6, 2.0, 1e-3, 400, 8, 2, 4, 2048, 256, 2.0),
+    (0, 7, 7, 1.0, 1e-3, 300, 9, 1, 2, 2048, 512, float("inf")),
+    (0, 7, 7, 1.0, 1e-3, 300, 10, 1, 2, 2048, 512, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"m{c[0]}_M{c[1]}N{c[2]}_W{c[7]}_B{c[8]}")
+def test_single_step_bit_exact(orc, case):
+    model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel = case
+    r = one_step(orc, model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel=t_rel)
+    check_parity(*r)
+
+
+def test_single_step_momentum_c3_sector(orc):
+    # the benchmark model (M = N = 16, u = 4, dtau = 5e-4) in the K = 0 sector
+    r = one_step(orc, 1, 16, 16, 4.0, 5e-4, 3000, 11, 1, 16, 4096, 512, sector=0)
+    check_parity(*r)
+
+
+def test_single_step_threshold_and_tiny_values(orc):
+    # theta = 0.5 and many sub-threshold amplitudes (compression path)
+    r = one_step(orc, 0, 9, 9, 3.0, 2e-3, 800, 12, 1, 8, 2048, 512, theta=0.5, lo=0.01, hi=2.0)
+    check_parity(*r)
+
+
+@pytest.mark.parametrize("M,N,W", [(32, 31, 1), (64, 63, 2)])
+def test_single_step_largest_addresses(orc, M, N, W):
+    # N+M-1 = 62 bits in one word, 126 bits in two words
+    r = one_step(orc, 0, M, N, 1.0, 1e-3, 500, 13, W, 8, 2048, 512)
+    check_parity(*r)
+
+
+def test_single_entry_state(orc):
+    r = one_step(orc, 0, 6, 6, 6.0, 1e-2, 1, 14, 1, 1, 1024, 256)
+    check_parity(*r)
+
+
+def _c1_gpu(steps, buckets=0, slots=0, block=0):
+    fq = _fq()
+    c = synthetic.CONFIGS["c1"]
+    s = fq.Solver(c["model"], c["M"], c["N"], t=c["t"], u=c["u"], dtau=c["dtau"],
+                  target_walkers=c["target"], seed=c["seed"], addr_words=1, table_capacity=1024,
+                  spawn_capacity=8192, buckets=buckets, lds_slots=slots, block=block)
+    a = fq.start_address(c["model"], c["M"], c["N"])
+    s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    st = s.run(steps)
+    s.close()
+    return st
+
+
+def test_c1_trajectory_bit_exact_vs_oracle(orc):
+    """Config 1 end to end (1e4 steps): every statistics row of the GPU run
+    equals the oracle's bit for bit."""
+    _flush("[c1 trajectory] 10000 steps")
+    c = synthetic.CONFIGS["c1"]
+    st = _c1_gpu(c["steps"])
+    P = orc.params(c["model"], c["M"], c["N"], c["t"], c["u"], dtau=c["dtau"], target=c["target"],
+                   seed=c["seed"])
+    a = orc.start_address(c["model"], c["M"], c["N"])
+    ost, _, _ = orc.run(P, [a], [10.0], 0.0, 1, c["steps"], a, 10.0)
+    for f in ost.dtype.names:
+        g, o = st[f], ost[f]
+        if g.dtype.kind == "f":
+            bad = np.nonzero(g.view(np.uint64) != o.view(np.uint64))[0]
+        else:
+            bad = np.nonzero(g != o)[0]
+        assert len(bad) == 0, (f, bad[:5], g[bad[:5]], o[bad[:5]])
+
+
+def test_c1_energy_within_3_sigma_of_ed(orc):
+    from oracle import stats
+    st = _c1_gpu(10_000)
+    E0 = orc.eigs_sparse(orc.ham(0, 6, 6, 1.0, 6.0), 1)[0]
+    se = stats.shift_estimator(st["shift"], skip=2000)
+    pe = stats.projected_energy(st["hproj"], st["vproj"], skip=2000)
+    _flush(f"[c1 energy] shift {se.mean:.5f} +- {se.err:.5f}  proj {pe.ratio:.5f} +- {pe.err:.5f}  "
+           f"E0 {E0:.8f}")
+    assert abs(se.mean - E0) < 3 * se.err
+    assert abs(pe.ratio - E0) < 3 * pe.err
+
+
+def test_schedule_independence():
+    """Bucket count, LDS table size and workgroup size do not change a bit."""
+    ref = _c1_gpu(3000)
+    for B, slots, block in [(1, 1024, 256), (8, 1024, 1024), (64, 4096, 512), (2, 8192, 1024)]:
+        st = _c1_gpu(3000, B, slots, block)
+        assert st.tobytes() == ref.tobytes(), (B, slots, block)
