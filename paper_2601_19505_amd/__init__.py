@@ -69,6 +69,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2601_19505_amd.build` (hipcc, gfx950)")
+        # PyTorch ships its own HIP runtime under the same soname; load it
+        # first so the library binds to it and the process has one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, vp = C.POINTER, C.c_void_p
         u64p, f64p, i64p, i32p = P(C.c_uint64), P(C.c_double), P(C.c_int64), P(C.c_int32)
@@ -123,7 +129,8 @@ def workspace_size(ham, params, layout):
     rc = lib().fq_workspace_size(C.byref(ham), C.byref(params), C.byref(layout), C.byref(nb),
                                  C.byref(lo))
     if rc:
-        raise FqError(rc, "fq_workspace_size: invalid parameters or layout")
+        msg = lib().fq_last_error(None)
+        raise FqError(rc, f"fq_workspace_size: {msg.decode() if msg else ''}")
     return nb.value, lo
 
 
@@ -157,7 +164,8 @@ class Solver:
         rc = lib().fq_create(C.byref(self.ham), C.byref(self.params), C.byref(lay),
                              C.c_void_p(self.ws.data_ptr()), nbytes, C.byref(h))
         if rc:
-            raise FqError(rc, "fq_create")
+            msg = lib().fq_last_error(None)
+            raise FqError(rc, f"fq_create: {msg.decode() if msg else ''}")
         self.h = h
         self.table_capacity = lay.table_capacity
         self.spawn_capacity = lay.spawn_capacity

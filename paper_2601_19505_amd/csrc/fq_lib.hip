@@ -317,9 +317,13 @@ struct fq_handle {
     std::vector<int> ref_bucket_host;
 };
 
+static thread_local std::string g_err;  // errors of calls that have no handle yet
+
 static int hip_fail(fq_handle *q, hipError_t e, const char *what)
 {
-    if (q) q->err = std::string(what) + ": " + hipGetErrorString(e);
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (q) q->err = m;
+    g_err = m;
     return FQ_EHIP;
 }
 
@@ -396,7 +400,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     fq_handle *q = new (std::nothrow) fq_handle();
     if (!q) return FQ_ENOMEM;
     int rc = resolve(h, p, layout, q->R, q->L, q->err);
-    if (rc) { delete q; return rc; }
+    if (rc) { g_err = q->err; delete q; return rc; }
     if (!workspace || bytes < q->R.total || ((uintptr_t)workspace & 255)) {
         delete q;
         return workspace ? FQ_ENOMEM : FQ_EINVAL;
@@ -459,13 +463,15 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
-    HIPCHK(q, hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice));
-    HIPCHK(q, hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice));
-    HIPCHK(q, hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice));
-    HIPCHK(q, hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl)));
     const void *kf = step_kernel(R.W, h->model, R.block);
     size_t lb = lds_bytes(R.W, h->model, R.slots, R.block);
-    HIPCHK(q, hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb));
+    hipError_t e = hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl));
+    if (e != hipSuccess) { hip_fail(q, e, "fq_create: workspace initialisation"); delete q; return FQ_EHIP; }
+    e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb);
+    if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernel)"); delete q; return FQ_EHIP; }
     q->ring_host.resize(RING);
     *out = q;
     return FQ_OK;
@@ -479,7 +485,7 @@ int fq_destroy(fq_handle *q)
     return FQ_OK;
 }
 
-const char *fq_last_error(const fq_handle *q) { return q ? q->err.c_str() : "null handle"; }
+const char *fq_last_error(const fq_handle *q) { return q ? q->err.c_str() : g_err.c_str(); }
 
 int fq_get_layout(const fq_handle *q, fq_layout *layout)
 {

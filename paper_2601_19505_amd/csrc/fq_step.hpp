@@ -482,9 +482,9 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             info[2 * i] = (u32)ubase;
             ubase += ((info[2 * i + 1] & 0x7fffffffu) + 3) / 4;
         }
-        // spawn statistics for row (spawn_step - 1)
+        // spawn statistics belong to row spawn_step (parents of c^(spawn_step - 1))
         {
-            i64 *acc = ctrl->spawn_acc[(spawn_step - 1) & 1];
+            i64 *acc = ctrl->spawn_acc[spawn_step & 1];
             if (nex) atomicAdd((unsigned long long *)&acc[0], (unsigned long long)nex);
             if (nin) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)nin);
             if (nsp) atomicAdd((unsigned long long *)&acc[2], (unsigned long long)nsp);
