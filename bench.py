@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--diag", action="store_true", help="per-phase kernel timers (diagnostics)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
@@ -112,7 +113,7 @@ def main():
     steps = wl["steps"] if args.steps is None else args.steps
     warmup = wl["warmup"] if args.warmup is None else args.warmup
     torch.cuda.set_device(0)
-    s = make_solver(fq, wl, cfg)
+    s = make_solver(fq, wl, cfg, **({"flags": fq.FLAG_PHASE_TIMING} if args.diag else {}))
     occ = synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"])
     a = fq.encode(occ, cfg["W"])
     s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
@@ -132,6 +133,8 @@ def main():
     torch.cuda.synchronize()
     s.set_timing(True)
     s.kernel_time(reset=True)
+    if args.diag:
+        s.debug_counters(reset=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.run(steps)
@@ -139,6 +142,9 @@ def main():
     wall = time.perf_counter() - t1
     kms, nl = s.kernel_time()
     s.set_timing(False)
+    if args.diag:
+        d = s.debug_counters()
+        log("[bench] diag " + json.dumps({k: round(v, 3) for k, v in d.items()}))
     log(f"[bench] timed {steps} steps in {wall:.3f} s; norm {st['norm'][-1]:.4g} len {st['len'][-1]}")
     walker_steps = float(st["norm"].sum())
     value = walker_steps / wall

@@ -82,6 +82,7 @@ typedef struct {
 /* Flags of fq_params.flags */
 #define FQ_FLAG_DUMP_SPAWNS 1   /* record every spawn event (parity testing)      */
 #define FQ_FLAG_DUMP_MERGED 2   /* record every merged pre-compression amplitude  */
+#define FQ_FLAG_PHASE_TIMING 4  /* accumulate per-phase timers (diagnostics)      */
 
 /* Algorithm parameters.  dtau: time step (Sec. 3.1); target_walkers: N_t;
  * zeta, xi: shift damping and forcing (Eq. shift-update; defaults 0.08 and
@@ -160,7 +161,13 @@ int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap
 int fq_set_timing(fq_handle *q, int32_t enable);
 int fq_kernel_time(fq_handle *q, double *ms, int64_t *launches, int32_t reset);
 
-/* Current layout (with defaults resolved) and largest LDS load seen. */
+/* Diagnostics (flag FQ_FLAG_PHASE_TIMING): out[0..9] = summed wall-clock
+ * milliseconds per phase of the step kernel (workgroup-summed), out[10] =
+ * LDS hash probes, out[11] = inserts per thread summed, out[12] = largest
+ * number of distinct addresses in one bucket.  n >= 13. */
+int fq_debug_counters(fq_handle *q, double *out, int32_t n, int32_t reset, void *stream);
+
+/* Current layout (with defaults resolved). */
 int fq_get_layout(const fq_handle *q, fq_layout *layout);
 
 int fq_destroy(fq_handle *q);

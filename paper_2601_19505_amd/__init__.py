@@ -20,6 +20,7 @@ MOM1D = 1
 
 FLAG_DUMP_SPAWNS = 1
 FLAG_DUMP_MERGED = 2
+FLAG_PHASE_TIMING = 4
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ENOMEM", -5: "EBUSY",
           -6: "EDIVERGED", -7: "ENOTFOUND"}
@@ -93,6 +94,7 @@ def lib():
             "fq_set_timing": (C.c_int, [vp, C.c_int32]),
             "fq_kernel_time": (C.c_int, [vp, f64p, i64p, C.c_int32]),
             "fq_get_layout": (C.c_int, [vp, P(Layout)]),
+            "fq_debug_counters": (C.c_int, [vp, f64p, C.c_int32, C.c_int32, vp]),
             "fq_destroy": (C.c_int, [vp]),
             "fq_last_error": (C.c_char_p, [vp]),
         }
@@ -217,17 +219,23 @@ class Solver:
         return out
 
     def get_state(self, cap=None):
+        """Current state (addresses, values, shift, step); order unspecified."""
         if cap is None:
             cap = self.table_capacity + 1024
-        a = np.zeros((cap, self.W), np.uint64)
-        v = np.zeros(cap, np.float64)
-        n = C.c_int64(0)
-        sh = C.c_double(0)
-        st = C.c_int64(0)
-        self._check(lib().fq_get_state(self.h, _p(a, C.c_uint64), _p(v, C.c_double), cap,
-                                       C.byref(n), C.byref(sh), C.byref(st), _stream()),
-                    "fq_get_state")
-        return a[:n.value].copy(), v[:n.value].copy(), sh.value, st.value
+        for _ in range(2):
+            a = np.zeros((cap, self.W), np.uint64)
+            v = np.zeros(cap, np.float64)
+            n = C.c_int64(0)
+            sh = C.c_double(0)
+            st = C.c_int64(0)
+            rc = lib().fq_get_state(self.h, _p(a, C.c_uint64), _p(v, C.c_double), cap, C.byref(n),
+                                    C.byref(sh), C.byref(st), _stream())
+            if rc == -2 and n.value > cap:
+                cap = n.value
+                continue
+            self._check(rc, "fq_get_state")
+            return a[:n.value].copy(), v[:n.value].copy(), sh.value, st.value
+        raise FqError(-2, "fq_get_state: state changed size")
 
     def spawn_dump(self, cap=None):
         cap = cap or (self.spawn_capacity + self.table_capacity)
@@ -260,6 +268,16 @@ class Solver:
         self._check(lib().fq_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0),
                     "fq_kernel_time")
         return ms.value, n.value
+
+    def debug_counters(self, reset=False):
+        out = np.zeros(13)
+        self._check(lib().fq_debug_counters(self.h, _p(out, C.c_double), 13, 1 if reset else 0,
+                                            _stream()), "fq_debug_counters")
+        names = ["init", "merge_table", "merge_slab", "compress", "compact", "spawn_info",
+                 "scan", "spawn", "diag_reduce", "ph9"]
+        d = {f"ms_{n}": float(out[i]) for i, n in enumerate(names)}
+        d.update(probes=float(out[10]), inserts=float(out[11]), max_load=float(out[12]))
+        return d
 
     def get_layout(self):
         lo = Layout()

@@ -28,6 +28,8 @@ __global__ __launch_bounds__(BS) void k_step(const Inst *I, int mode)
     process_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, mode, smem);
 }
 
+__global__ __launch_bounds__(1024) void k_finalize(const Inst *I) { finalize_instance<1024>(*I); }
+
 // insert host-staged entries into table[parity] and accumulate the norm
 template <int W>
 __global__ __launch_bounds__(256) void k_insert(const Inst *Ip, const u64 *sa, const double *sv, i64 n)
@@ -196,7 +198,7 @@ struct Resolved {
     i64 cap_t, cap_s, dump_cap;
     size_t off_ctrl, off_inst, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
-        off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, total;
+        off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], total;
     int nsq;
 };
 
@@ -273,6 +275,9 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     R.off_ref_off = take(sizeof(int) * (R.B + 1));
     R.off_ref_tmp = take((sizeof(u64) * 2 + sizeof(double) + sizeof(int)) * REFCAP + 64);
     R.off_ring = take(sizeof(StepStats) * RING);
+    R.off_part = take(sizeof(Part) * R.B);
+    R.off_spart[0] = take(sizeof(SpawnPart) * R.B);
+    R.off_spart[1] = take(sizeof(SpawnPart) * R.B);
     const i64 tn = (i64)R.B * R.cap_t;
     for (int q = 0; q < 2; q++) {
         R.off_tab_a[q][0] = take(sizeof(u64) * tn);
@@ -332,6 +337,8 @@ static int hip_fail(fq_handle *q, hipError_t e, const char *what)
         hipError_t e_ = (call);                           \
         if (e_ != hipSuccess) return hip_fail(q, e_, #call); \
     } while (0)
+
+static int read_ctrl(fq_handle *q, Ctrl &c, hipStream_t s);
 
 static const char *fqe_name(int e)
 {
@@ -456,6 +463,9 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     I.dmg_addr = (u64 *)(q->ws + R.off_dmg_addr);
     I.dmg_val = (double *)(q->ws + R.off_dmg_val);
     I.dump_cap = R.dump_cap;
+    I.part = (Part *)(q->ws + R.off_part);
+    I.spart[0] = (SpawnPart *)(q->ws + R.off_spart[0]);
+    I.spart[1] = (SpawnPart *)(q->ws + R.off_spart[1]);
     q->d_inst = (Inst *)(q->ws + R.off_inst);
     q->d_ctrl = I.ctrl;
     // host tables: correctly rounded square roots and the momentum dispersion
@@ -486,6 +496,32 @@ int fq_destroy(fq_handle *q)
 }
 
 const char *fq_last_error(const fq_handle *q) { return q ? q->err.c_str() : g_err.c_str(); }
+
+int fq_debug_counters(fq_handle *q, double *out, int32_t n, int32_t reset, void *stream)
+{
+    if (!q || !out || n < 13) return FQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Ctrl c;
+    int rc = read_ctrl(q, c, s);
+    if (rc) return rc;
+    int rate = 0;
+    HIPCHK(q, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, 0));
+    for (int k = 0; k < 10; k++) out[k] = rate > 0 ? (double)c.phase[k] / ((double)rate * 1e3) * 1e3 : 0.0;  // ms
+    out[10] = (double)c.probes;
+    out[11] = (double)c.inserts;
+    out[12] = (double)c.max_load;
+    if (reset) {
+        Ctrl z = c;
+        memset(z.phase, 0, sizeof z.phase);
+        z.probes = z.inserts = 0;
+        z.max_load = 0;
+        HIPCHK(q, hipMemcpyAsync(&q->d_ctrl->phase, &z.phase, sizeof z.phase, hipMemcpyHostToDevice, s));
+        HIPCHK(q, hipMemcpyAsync(&q->d_ctrl->probes, &z.probes, 16, hipMemcpyHostToDevice, s));
+        HIPCHK(q, hipMemcpyAsync(&q->d_ctrl->max_load, &z.max_load, 4, hipMemcpyHostToDevice, s));
+        HIPCHK(q, hipStreamSynchronize(s));
+    }
+    return FQ_OK;
+}
 
 int fq_get_layout(const fq_handle *q, fq_layout *layout)
 {
@@ -676,6 +712,7 @@ int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream
             int rc = launch_step(q, 0, s);
             if (rc) return rc;
             if (q->timing) HIPCHK(q, hipEventRecord(q->ev[2 * k + 1], s));
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, (const Inst *)q->d_inst);
         }
         Ctrl c;
         int rc = read_ctrl(q, c, s);

@@ -43,16 +43,27 @@ struct Ctrl {
     int error;         // 0 or an FQE_* code
     double shift;      // S^(n)
     double norm;       // ||c^(n)||_1
-    u32 done;          // completion counter of the running step
+    u32 pad1;
     u32 max_load;      // largest LDS hash occupancy seen
     i64 ring_base;     // step number stored in ring row 0
-    u64 acc_norm[2], acc_hproj[2], acc_vproj[2];
-    i64 acc_len;
-    i64 spawn_acc[2][4];  // per row parity: exact, inexact, spawns
+    u64 acc_norm[2];   // norm of a state being set (set_state only)
     i64 dump_spawn_n, dump_merged_n;
     i64 stop_step;     // batch: do not advance past this step
     int err_bucket, pad0;
-    i64 pad[4];
+    u64 phase[10];     // summed wall-clock ticks per phase (opt-in diagnostics)
+    u64 probes;        // LDS hash probes summed over all inserts (diagnostics)
+    u64 inserts;
+};
+
+// per-bucket partial statistics, written with plain stores by the workgroup
+// that merges the bucket and reduced by the finalize kernel (no same-address
+// atomics on the step's critical path)
+struct Part {
+    u64 norm[2], hproj[2], vproj[2];
+    i64 len, load;
+};
+struct SpawnPart {
+    i64 exact, inexact, spawns, pad;
 };
 
 struct Inst {
@@ -81,6 +92,8 @@ struct Inst {
     u64 *dmg_addr;
     double *dmg_val;
     i64 dump_cap;
+    Part *part;          // [B]
+    SpawnPart *spart[2]; // [row parity][B]
 };
 
 __device__ __forceinline__ void set_error(Ctrl *c, int code, int bucket)
@@ -171,10 +184,11 @@ struct Lds {
 };
 
 // find or insert the slot of address (a0, a1); returns -1 when full
-template <int W> __device__ __forceinline__ int lds_slot(const Lds &L, u64 a0, u64 a1, u64 h)
+template <int W> __device__ __forceinline__ int lds_slot(const Lds &L, u64 a0, u64 a1, u64 h, int &np)
 {
     int s = (int)(h & (u64)L.mask);
     for (int probe = 0; probe <= L.mask; probe++) {
+        np++;
         if (W == 1) {
             u64 k = __hip_atomic_load(&L.k0[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (k == a0) return s;
@@ -220,11 +234,11 @@ template <int W> __device__ __forceinline__ int lds_find(const Lds &L, u64 a0, u
 }
 
 template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Inst &I, u64 a0, u64 a1,
-                                                        double v, int b)
+                                                        double v, int b, int &np)
 {
     typedef typename AddrOf<W>::T T;
     u64 h = addr_hash(AddrOf<W>::make(a0, a1));
-    int s = lds_slot<W>(L, a0, a1, h);
+    int s = lds_slot<W>(L, a0, a1, h, np);
     if (s < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); return; }
     u64 lo, hi;
     int ovf = 0;
@@ -268,7 +282,6 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
     const int tid = threadIdx.x;
     Ctrl *ctrl = I.ctrl;
     const int slots = I.slots;
-    __shared__ int s_flag;
     __shared__ int s_err;
 
     if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -292,6 +305,16 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
     L.mask = slots - 1;
     unsigned char *myrow = L.rows + (size_t)tid * MOM_ROW;
 
+    const bool timing = (I.flags & 4) != 0;
+    u64 tprev = timing ? wall_clock64() : 0;
+    auto mark = [&](int ph) {
+        if (timing && tid == 0) {
+            u64 t = wall_clock64();
+            atomicAdd((unsigned long long *)&ctrl->phase[ph], (unsigned long long)(t - tprev));
+            tprev = t;
+        }
+    };
+    int nprobe = 0;
     const int out_par = mode == 0 ? 1 - p : p;
     const u32 spawn_step = (u32)(mode == 0 ? n + 2 : n + 1);
     int nS = 0;  // survivors held in LDS for the spawn phase
@@ -306,6 +329,7 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
         }
         if (tid < 64) L.misc[tid] = 0;
         __syncthreads();
+        mark(0);
         const int nt = I.tab_n[p][b];
         const i64 tb = (i64)b * I.cap_t;
         for (int i = tid; i < nt; i += BS) {
@@ -317,17 +341,30 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             if (MODEL == 0) hii = real_diag(I.mc, a);
             else { MomRow R = mom_row(myrow); mom_decode(I.mc, a, R); hii = mom_diag(I.mc, R); }
             double g = 1.0 + I.dtau * (S - hii);
-            lds_add<W>(L, I, a0, a1, c * g, b);
+            lds_add<W>(L, I, a0, a1, c * g, b, nprobe);
         }
+        if (timing) { __syncthreads(); mark(1); }
         const int ns = min(I.slab_n[p][b], (int)I.cap_s);
         const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)sizeof(Rec<W>);
         for (int i = tid; i < ns; i += BS) {
             u64 a0, a1;
             double v;
             load_rec<W>(sb, i, a0, a1, v);
-            lds_add<W>(L, I, a0, a1, v, b);
+            lds_add<W>(L, I, a0, a1, v, b, nprobe);
         }
         __syncthreads();
+        mark(2);
+        if (timing) {
+            i64 tp, ti;
+            block_excl_scan<BS>((i64)nprobe, L.misc, tp);
+            i64 mine_ins = (nt > tid ? (nt - tid + BS - 1) / BS : 0) + (ns > tid ? (ns - tid + BS - 1) / BS : 0);
+            block_excl_scan<BS>(mine_ins, L.misc, ti);
+            if (tid == 0) {
+                atomicAdd((unsigned long long *)&ctrl->probes, (unsigned long long)tp);
+                atomicAdd((unsigned long long *)&ctrl->inserts, (unsigned long long)ti);
+            }
+            mark(8);
+        }
 
         // ------------------------------------------------ 2. compress (per slot, owner thread)
         const int spt = slots / BS;  // slots per thread (contiguous), <= 8
@@ -374,6 +411,7 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
                 add128(nlo, nhi, lo, hi);
             }
         }
+        mark(3);
         // expose compressed values for the projected-energy lookups
 #pragma unroll
         for (int k = 0; k < 8; k++)
@@ -381,6 +419,8 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
         __syncthreads();
 
         // ------------------------------------------------ 3. projected energy
+        if (tid == 0) { L.misc[42] = 0; L.misc[43] = 0; L.misc[44] = 0; L.misc[45] = 0; }
+        __syncthreads();
         {
             const int r_beg = I.ref_off[b], r_end = I.ref_off[b + 1];
             for (int e = r_beg + tid; e < r_end; e += BS) {
@@ -393,10 +433,10 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
                 u64 lo, hi;
                 int ovf = 0;
                 to_fixed(term, lo, hi, ovf);
-                glb_acc128(ctrl->acc_hproj, lo, hi);
+                lds_acc128((u64 *)&L.misc[42], (u64 *)&L.misc[43], lo, hi);
                 if (e == I.ref_self) {
                     to_fixed(I.yref * cv, lo, hi, ovf);
-                    glb_acc128(ctrl->acc_vproj, lo, hi);
+                    lds_acc128((u64 *)&L.misc[44], (u64 *)&L.misc[45], lo, hi);
                 }
             }
         }
@@ -405,7 +445,7 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             i64 tot;
             i64 u = block_excl_scan<BS>(used, L.misc, tot);
             (void)u;
-            if (tid == 0 && tot > 0) atomicMax(&ctrl->max_load, (u32)tot);
+            if (tid == 0) L.misc[46] = tot;
         }
         // ------------------------------------------------ 4. compact
         i64 total;
@@ -437,12 +477,19 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
         __syncthreads();
         if (tid == 0) {
             I.tab_n[out_par][b] = (int)total;
-            if (total) {
-                atomicAdd((unsigned long long *)&ctrl->acc_len, (unsigned long long)total);
-                glb_acc128(ctrl->acc_norm, (u64)L.misc[40], (u64)L.misc[41]);
-            }
+            Part pt;
+            pt.norm[0] = (u64)L.misc[40];
+            pt.norm[1] = (u64)L.misc[41];
+            pt.hproj[0] = (u64)L.misc[42];
+            pt.hproj[1] = (u64)L.misc[43];
+            pt.vproj[0] = (u64)L.misc[44];
+            pt.vproj[1] = (u64)L.misc[45];
+            pt.len = total;
+            pt.load = L.misc[46];
+            I.part[b] = pt;
         }
         nS = (int)total;
+        mark(4);
     } else {
         // spawn-only pass: survivors are the stored entries of table[p]
         nS = I.tab_n[p][b];
@@ -476,6 +523,7 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             if (ex) nex++; else nin++;
         }
         if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
+        mark(5);
         i64 utot;
         i64 ubase = block_excl_scan<BS>(units, L.misc, utot);
         for (int i = i0; i < i1; i++) {
@@ -484,13 +532,21 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
         }
         // spawn statistics belong to row spawn_step (parents of c^(spawn_step - 1))
         {
-            i64 *acc = ctrl->spawn_acc[spawn_step & 1];
-            if (nex) atomicAdd((unsigned long long *)&acc[0], (unsigned long long)nex);
-            if (nin) atomicAdd((unsigned long long *)&acc[1], (unsigned long long)nin);
-            if (nsp) atomicAdd((unsigned long long *)&acc[2], (unsigned long long)nsp);
+            i64 t_ex, t_in, t_sp;
+            block_excl_scan<BS>(nex, L.misc, t_ex);
+            block_excl_scan<BS>(nin, L.misc, t_in);
+            block_excl_scan<BS>(nsp, L.misc, t_sp);
+            if (tid == 0) {
+                SpawnPart sp;
+                sp.exact = t_ex;
+                sp.inexact = t_in;
+                sp.spawns = t_sp;
+                sp.pad = 0;
+                I.spart[spawn_step & 1][b] = sp;
+            }
         }
-        __syncthreads();
 
+        mark(6);
         char *ob = I.slab[out_par];
         int *on = I.slab_n[out_par];
         const double dtau = I.dtau;
@@ -573,69 +629,109 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             }
         }
     }
-    if (mode != 0) return;
+    if (timing) { __syncthreads(); mark(7); }
+}
 
-    // ---------------------------------------------------- finalize (last workgroup)
-    __threadfence();
+// ---------------------------------------------------------------- finalize
+
+// One workgroup: reduce the per-bucket partials of the step that just ran,
+// update the shift (Eq. shift-update), write the statistics row, release the
+// consumed spawn slab.  Exact integer reductions, so the result does not
+// depend on the number of buckets.
+template <int BS> __device__ void finalize_instance(const Inst &I)
+{
+    __shared__ u64 red[BS / 64][12];
+    __shared__ int s_err;
+    Ctrl *ctrl = I.ctrl;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    if (tid == 0) {
-        u32 prev = atomicAdd(&ctrl->done, 1u);
-        s_flag = prev == (u32)(I.B - 1);
+    if (s_err) return;
+    const i64 n = ctrl->step;
+    const int p = ctrl->parity;
+    const double S = ctrl->shift;
+    u64 nl = 0, nh = 0, hl = 0, hh = 0, vl = 0, vh = 0;
+    i64 len = 0, load = 0, ex = 0, in = 0, sp = 0;
+    const SpawnPart *spp = I.spart[(n + 1) & 1];
+    for (int b = tid; b < I.B; b += BS) {
+        const Part pt = I.part[b];
+        add128(nl, nh, pt.norm[0], pt.norm[1]);
+        add128(hl, hh, pt.hproj[0], pt.hproj[1]);
+        add128(vl, vh, pt.vproj[0], pt.vproj[1]);
+        len += pt.len;
+        load = max(load, pt.load);
+        const SpawnPart q = spp[b];
+        ex += q.exact;
+        in += q.inexact;
+        sp += q.spawns;
+    }
+    // wave reduction (integer adds are exact and associative)
+    for (int o = 32; o > 0; o >>= 1) {
+        u64 x = __shfl_down(nl, o, 64), y = __shfl_down(nh, o, 64);
+        add128(nl, nh, x, y);
+        x = __shfl_down(hl, o, 64); y = __shfl_down(hh, o, 64);
+        add128(hl, hh, x, y);
+        x = __shfl_down(vl, o, 64); y = __shfl_down(vh, o, 64);
+        add128(vl, vh, x, y);
+        len += __shfl_down(len, o, 64);
+        load = max(load, (i64)__shfl_down(load, o, 64));
+        ex += __shfl_down(ex, o, 64);
+        in += __shfl_down(in, o, 64);
+        sp += __shfl_down(sp, o, 64);
+    }
+    if (lane == 0) {
+        red[wid][0] = nl; red[wid][1] = nh; red[wid][2] = hl; red[wid][3] = hh;
+        red[wid][4] = vl; red[wid][5] = vh; red[wid][6] = (u64)len; red[wid][7] = (u64)load;
+        red[wid][8] = (u64)ex; red[wid][9] = (u64)in; red[wid][10] = (u64)sp;
     }
     __syncthreads();
-    if (!s_flag) return;
-    __threadfence();
     if (tid == 0) {
-        int err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_err = err;
-        if (!err) {
-            u64 *an = ctrl->acc_norm, *ah = ctrl->acc_hproj, *av = ctrl->acc_vproj;
-            double N1 = from_fixed(__hip_atomic_load(&an[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                   __hip_atomic_load(&an[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            double hp = from_fixed(__hip_atomic_load(&ah[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                   __hip_atomic_load(&ah[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            double vp = from_fixed(__hip_atomic_load(&av[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                   __hip_atomic_load(&av[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            i64 len = __hip_atomic_load(&ctrl->acc_len, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            double N0 = ctrl->norm;
-            double S1 = S;
-            if (N1 > 0.0) {
-                double za = I.zeta / I.dtau, xb = I.xi / I.dtau;
-                S1 = (S - za * det_log(N1 / N0)) - xb * det_log(N1 / I.target);
-            }
-            if (!(N1 < 17592186044416.0) || !(S1 == S1)) {
-                set_error(ctrl, FQE_DIVERGED, -1);
-                s_err = 1;
-            } else {
-                i64 *sa = ctrl->spawn_acc[(n + 1) & 1];
-                i64 row = n + 1 - ctrl->ring_base;
-                if (row >= 0 && row < I.ring_cap) {
-                    StepStats &R = I.ring[row];
-                    R.step = n + 1;
-                    R.len = len;
-                    R.exact_steps = __hip_atomic_load(&sa[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    R.inexact_steps = __hip_atomic_load(&sa[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    R.spawns = __hip_atomic_load(&sa[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    R.shift = S1;
-                    R.norm = N1;
-                    R.hproj = hp;
-                    R.vproj = vp;
-                }
-                sa[0] = sa[1] = sa[2] = 0;
-                an[0] = an[1] = ah[0] = ah[1] = av[0] = av[1] = 0;
-                ctrl->acc_len = 0;
-                ctrl->shift = S1;
-                ctrl->norm = N1;
-                ctrl->step = n + 1;
-                ctrl->parity = 1 - p;
-            }
+        for (int w = 1; w < BS / 64; w++) {
+            add128(nl, nh, red[w][0], red[w][1]);
+            add128(hl, hh, red[w][2], red[w][3]);
+            add128(vl, vh, red[w][4], red[w][5]);
+            len += (i64)red[w][6];
+            load = max(load, (i64)red[w][7]);
+            ex += (i64)red[w][8];
+            in += (i64)red[w][9];
+            sp += (i64)red[w][10];
         }
-        ctrl->done = 0;
+        const double N1 = from_fixed(nl, nh);
+        const double hp = from_fixed(hl, hh);
+        const double vp = from_fixed(vl, vh);
+        const double N0 = ctrl->norm;
+        double S1 = S;
+        if (N1 > 0.0) {
+            const double za = I.zeta / I.dtau, xb = I.xi / I.dtau;
+            S1 = (S - za * det_log(N1 / N0)) - xb * det_log(N1 / I.target);
+        }
+        if ((u32)load > ctrl->max_load) ctrl->max_load = (u32)load;
+        if (!(N1 < 17592186044416.0) || !(S1 == S1)) {
+            set_error(ctrl, FQE_DIVERGED, -1);
+            s_err = 1;
+        } else {
+            const i64 row = n + 1 - ctrl->ring_base;
+            if (row >= 0 && row < I.ring_cap) {
+                StepStats &R = I.ring[row];
+                R.step = n + 1;
+                R.len = len;
+                R.exact_steps = ex;
+                R.inexact_steps = in;
+                R.spawns = sp;
+                R.shift = S1;
+                R.norm = N1;
+                R.hproj = hp;
+                R.vproj = vp;
+            }
+            ctrl->shift = S1;
+            ctrl->norm = N1;
+            ctrl->step = n + 1;
+            ctrl->parity = 1 - p;
+        }
     }
     __syncthreads();
     if (s_err) return;
     for (int i = tid; i < I.B; i += BS) I.slab_n[p][i] = 0;  // consumed spawns
-    __threadfence();
 }
 
 }  // namespace fq
