@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "c3": dict(cfg="c3", name="mom1d_M16_N16_u4_dtau5e-4_Nt1e8",
                table_capacity=19_500_000, spawn_capacity=200_000_000, buckets=8192,
-               lds_slots=4096, block=512, warmup=3000, steps=1000),
+               lds_slots=4096, block=1024, warmup=3000, steps=1000),
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
                table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=0,
                lds_slots=4096, block=1024, warmup=6000, steps=1000),
@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--diag", action="store_true", help="per-phase kernel timers (diagnostics)")
+    ap.add_argument("--buckets", type=int, default=None)
+    ap.add_argument("--slots", type=int, default=None)
+    ap.add_argument("--block", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
@@ -108,7 +111,10 @@ def main():
     import torch
     import paper_2601_19505_amd as fq
 
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    for k_arg, k_wl in (("buckets", "buckets"), ("slots", "lds_slots"), ("block", "block")):
+        if getattr(args, k_arg) is not None:
+            wl[k_wl] = getattr(args, k_arg)
     cfg = synthetic.CONFIGS[wl["cfg"]]
     steps = wl["steps"] if args.steps is None else args.steps
     warmup = wl["warmup"] if args.warmup is None else args.warmup
@@ -145,18 +151,30 @@ def main():
     if args.diag:
         d = s.debug_counters()
         log("[bench] diag " + json.dumps({k: round(v, 3) for k, v in d.items()}))
-    log(f"[bench] timed {steps} steps in {wall:.3f} s; norm {st['norm'][-1]:.4g} len {st['len'][-1]}")
+    log(f"[bench] timed {steps} steps in {wall:.3f} s; norm {st['norm'][-1]:.4g} len {st['len'][-1]}; "
+        f"kernel ms/step " + ", ".join(f"{k} {v / max(nl, 1):.3f}" for k, v in kms.items()))
     walker_steps = float(st["norm"].sum())
     value = walker_steps / wall
-    # algorithmic bytes of the launches: launch k reads c^(k-1) and the spawns
-    # of step k, writes c^(k) and the spawns of step k+1
+    # spawns of the step after the timed region (written by the last timed spawn launch)
+    nxt_last = float(s.run(1)["spawns"][-1])
+    # algorithmic HBM bytes per launch: merge k reads c^(k-1) and the spawn
+    # records of step k and writes c^(k); spawn k reads c^(k) and writes the
+    # spawn records of step k+1
     rec = 8 * cfg["W"] + 8
-    lens = np.concatenate([[prev["len"] if prev is not None else 1], st["len"]])
+    lens = np.concatenate([[prev["len"] if prev is not None else 1], st["len"]]).astype(np.float64)
     spw = st["spawns"].astype(np.float64)
-    nxt = np.concatenate([spw[1:], [spw[-1]]])
-    bytes_launch = rec * (lens[:-1] + spw + lens[1:] + nxt)
-    mean_kernel_s = kms / 1e3 / max(nl, 1)
-    achieved = float(bytes_launch.mean()) / mean_kernel_s / 1e9
+    nxt = np.concatenate([spw[1:], [nxt_last]])
+    per_kernel = {
+        "merge": float((rec * (lens[:-1] + spw + lens[1:])).mean()),
+        "spawn": float((rec * (lens[1:] + nxt)).mean()),
+    }
+    kern = {}
+    for k, b in per_kernel.items():
+        t_s = kms[k] / 1e3 / max(nl, 1)
+        kern[k] = {"mean_ms": t_s * 1e3, "algorithmic_bytes": b, "achieved_GBs": b / t_s / 1e9}
+    kern["partition"] = {"mean_ms": kms["partition"] / max(nl, 1)}
+    dom = max(per_kernel, key=lambda k: kern[k]["mean_ms"])
+    achieved = kern[dom]["achieved_GBs"]
     out = {
         "metric": "FCIQMC walker-steps/s at 1e8 walkers",
         "value": value,
@@ -180,9 +198,9 @@ def main():
                    "mean_spawns": float(st["spawns"].mean())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step (fused merge/compress/spawn)",
-                     "mean_kernel_ms": mean_kernel_s * 1e3,
-                     "algorithmic_bytes_per_launch": float(bytes_launch.mean())},
+                     "kernel": "k_" + dom, "mean_kernel_ms": kern[dom]["mean_ms"],
+                     "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"]},
+        "kernels": kern,
         "entry_steps_per_s": float(st["len"].sum()) / wall,
         "spawns_per_s": float(st["spawns"].sum()) / wall,
         "shift_mean": float(st["shift"].mean()),

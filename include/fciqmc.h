@@ -155,11 +155,15 @@ int fq_read_spawn_dump(fq_handle *q, uint64_t *parent, int64_t *attempt, uint64_
 int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap, int64_t *n,
                         void *stream);
 
-/* Total time (ms) and count of the fused step-kernel launches timed with
- * HIP events on the run stream since the last reset; timing is enabled
- * while `enable` is non-zero (it adds one event pair per launch). */
+/* Kernel timing with HIP events recorded on the run stream around the
+ * launches of each step while `enable` is non-zero (four events per step).
+ * fq_kernel_time fills ms[0..n-1] with the summed milliseconds since the
+ * last reset of: [0] the merge kernel (annihilation, compression, projected
+ * energy, compaction), [1] the spawn kernel, [2] the spawn partition and the
+ * shift update; entries beyond [2] are zero.  *steps receives the number of
+ * timed steps. */
 int fq_set_timing(fq_handle *q, int32_t enable);
-int fq_kernel_time(fq_handle *q, double *ms, int64_t *launches, int32_t reset);
+int fq_kernel_time(fq_handle *q, double *ms, int32_t n, int64_t *steps, int32_t reset);
 
 /* Diagnostics (flag FQ_FLAG_PHASE_TIMING): out[0..9] = summed wall-clock
  * milliseconds per phase of the step kernel (workgroup-summed), out[10] =

@@ -92,7 +92,7 @@ def lib():
             "fq_read_spawn_dump": (C.c_int, [vp, u64p, i64p, u64p, f64p, C.c_int64, i64p, vp]),
             "fq_read_merged_dump": (C.c_int, [vp, u64p, f64p, C.c_int64, i64p, vp]),
             "fq_set_timing": (C.c_int, [vp, C.c_int32]),
-            "fq_kernel_time": (C.c_int, [vp, f64p, i64p, C.c_int32]),
+            "fq_kernel_time": (C.c_int, [vp, f64p, C.c_int32, i64p, C.c_int32]),
             "fq_get_layout": (C.c_int, [vp, P(Layout)]),
             "fq_debug_counters": (C.c_int, [vp, f64p, C.c_int32, C.c_int32, vp]),
             "fq_destroy": (C.c_int, [vp]),
@@ -263,18 +263,21 @@ class Solver:
         self._check(lib().fq_set_timing(self.h, 1 if on else 0), "fq_set_timing")
 
     def kernel_time(self, reset=False):
-        ms = C.c_double(0)
+        """Summed HIP-event milliseconds of the timed steps as a dict with keys
+        merge, spawn, partition (spawn partition + shift update), and the
+        number of timed steps."""
+        ms = np.zeros(3)
         n = C.c_int64(0)
-        self._check(lib().fq_kernel_time(self.h, C.byref(ms), C.byref(n), 1 if reset else 0),
+        self._check(lib().fq_kernel_time(self.h, _p(ms, C.c_double), 3, C.byref(n), 1 if reset else 0),
                     "fq_kernel_time")
-        return ms.value, n.value
+        return dict(merge=float(ms[0]), spawn=float(ms[1]), partition=float(ms[2])), n.value
 
     def debug_counters(self, reset=False):
         out = np.zeros(13)
         self._check(lib().fq_debug_counters(self.h, _p(out, C.c_double), 13, 1 if reset else 0,
                                             _stream()), "fq_debug_counters")
         names = ["init", "merge_table", "merge_slab", "compress", "compact", "spawn_info",
-                 "scan", "spawn", "diag_reduce", "ph9"]
+                 "spawn_scan", "spawn_walk", "diag", "ph9"]
         d = {f"ms_{n}": float(out[i]) for i, n in enumerate(names)}
         d.update(probes=float(out[10]), inserts=float(out[11]), max_load=float(out[12]))
         return d

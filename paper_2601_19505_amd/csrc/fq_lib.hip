@@ -1,10 +1,14 @@
 // fq_lib.hip -- kernels and host runtime behind the C ABI of include/fciqmc.h.
 //
-// One plain step = one launch of k_step over the B buckets of an instance
-// (grid = B workgroups, one bucket each); the last workgroup to finish
-// performs the shift update, so there is no second launch and no host
-// synchronisation between steps.  The host only synchronises at the end of a
-// chunk of steps to copy the statistics rows and check the error word.
+// One step is four launches on the caller's stream with no host
+// synchronisation between them: k_merge (one workgroup per bucket:
+// annihilation, compression, projected energy, compaction into the other
+// table), k_spawn (one workgroup per bucket: spawn records of the new table
+// for the next step), k_part (second pass of the spawn partition, only when
+// there are more than 64 buckets) and k_finalize (one workgroup: exact
+// reduction of the per-bucket partial sums and the shift update).  The host
+// synchronises only at the end of a chunk of steps, to copy the statistics
+// rows and check the error word.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,13 +26,25 @@ using namespace fq;
 // ------------------------------------------------------------------ kernels
 
 template <int W, int MODEL, int BS>
-__global__ __launch_bounds__(BS) void k_step(const Inst *I, int mode)
+__global__ __launch_bounds__(BS) void k_merge(const Inst *I)
 {
     extern __shared__ __align__(16) char smem[];
-    process_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, mode, smem);
+    merge_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, smem);
+}
+
+template <int W, int MODEL, int BS>
+__global__ __launch_bounds__(BS) void k_spawn(const Inst *I, int mode)
+{
+    extern __shared__ __align__(16) char smem[];
+    spawn_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, mode, smem);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const Inst *I) { finalize_instance<1024>(*I); }
+
+template <int W> __global__ __launch_bounds__(1024) void k_part(const Inst *I)
+{
+    partition_coarse<W, 1024, 8>(*I, (int)blockIdx.x);
+}
 
 // insert host-staged entries into table[parity] and accumulate the norm
 template <int W>
@@ -77,38 +93,36 @@ __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *
 {
     const Inst &I = *Ip;
     typedef typename AddrOf<W>::T T;
-    __shared__ unsigned char row[MOM_ROW];
     if (threadIdx.x != 0) return;
-    T a = AddrOf<W>::make(r0, r1);
-    int k = 0;
+    const T a = AddrOf<W>::make(r0, r1);
     double hd;
     i64 m;
-    MomRow R = mom_row(row);
+    MomP<T> P = mom_parent(I.mc, a);
     if (MODEL == 0) {
         hd = real_diag(I.mc, a);
         m = 2 * popc(run_starts(a));
     } else {
-        mom_decode(I.mc, a, R);
-        hd = mom_diag(I.mc, R);
-        m = mom_m(R, I.mc.M);
+        hd = mom_diag(I.mc, P);
+        m = mom_m(P, I.mc.M);
     }
     if (m + 1 > cap) { *on = -1; return; }
     oa[0] = r0;
     oa[1] = r1;
     oh[0] = hd;
     ob[0] = (int)bucket_of(addr_hash(a), I.log2B);
-    k = 1;
-    T st = run_starts(a);
-    int o = popc(st);
+    int k = 1;
+    const T st = run_starts(a);
+    const int o = popc(st);
+    PairIt<T> it;
+    if (MODEL == 1 && m > 0) mom_it_init(P, I.mc.M, 0, it);
     for (i64 e = 0; e < m; e++) {
         double h;
         T d;
         if (MODEL == 0) {
             d = real_entry(I.mc, a, st, o, (int)e, h);
         } else {
-            int pp, qq, di;
-            mom_entry(R, I.mc.M, e, pp, qq, di);
-            d = mom_move(I.mc, a, R, pp, qq, di, h);
+            if (e > 0) mom_it_next(P, I.mc.M, it);
+            d = mom_move(I.mc, P, it.pa, it.pb, it.sa, it.sb, it.di, h);
         }
         oa[2 * k] = word0(d);
         oa[2 * k + 1] = word1(d);
@@ -147,29 +161,29 @@ __global__ void k_set_i64(i64 *p, i64 v) { *p = v; }
 namespace {
 
 constexpr i64 RING = 4096;
+constexpr int NEV = 4;  // timing events per step: merge | spawn | partition + finalize
 constexpr int REFCAP = 1 << 15;
 
-typedef void (*StepFn)(const Inst *, int);
-
-struct KernelSet {
-    const void *step;
-    int bs;
-};
-
 template <int W, int MODEL>
-const void *pick_step(int bs)
+const void *pick_kernel(int bs, bool spawn)
 {
     switch (bs) {
-    case 256: return (const void *)k_step<W, MODEL, 256>;
-    case 512: return (const void *)k_step<W, MODEL, 512>;
-    default: return (const void *)k_step<W, MODEL, 1024>;
+    case 256: return spawn ? (const void *)k_spawn<W, MODEL, 256> : (const void *)k_merge<W, MODEL, 256>;
+    case 512: return spawn ? (const void *)k_spawn<W, MODEL, 512> : (const void *)k_merge<W, MODEL, 512>;
+    default: return spawn ? (const void *)k_spawn<W, MODEL, 1024> : (const void *)k_merge<W, MODEL, 1024>;
     }
 }
 
-const void *step_kernel(int W, int model, int bs)
+// kernel variant: 0 real space, 1 momentum space with M <= 16, 2 momentum with M <= 32
+int variant(int model, int M) { return model == 0 ? 0 : (M <= 16 ? 1 : 2); }
+
+const void *step_kernel(int W, int var, int bs, bool spawn)
 {
-    if (W == 1) return model == 0 ? pick_step<1, 0>(bs) : pick_step<1, 1>(bs);
-    return model == 0 ? pick_step<2, 0>(bs) : pick_step<2, 1>(bs);
+    if (W == 1)
+        return var == 0 ? pick_kernel<1, 0>(bs, spawn) : var == 1 ? pick_kernel<1, 1>(bs, spawn)
+                                                                   : pick_kernel<1, 2>(bs, spawn);
+    return var == 0 ? pick_kernel<2, 0>(bs, spawn) : var == 1 ? pick_kernel<2, 1>(bs, spawn)
+                                                               : pick_kernel<2, 2>(bs, spawn);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -183,22 +197,27 @@ int ilog2(i64 x)
 
 size_t rec_bytes(int W) { return W == 1 ? 16 : 24; }
 
-size_t lds_bytes(int W, int model, int slots, int bs)
+// merge kernel: the LDS hash table (keys, 128-bit accumulators, W = 2 slot
+// states) and the scratch words
+size_t lds_bytes(int W, int slots)
 {
     size_t per = 8 + (W == 2 ? 8 : 0) + 8 + 8 + (W == 2 ? 4 : 0);
-    size_t b = (size_t)slots * per + 64 * 8;
-    if (model == 1) b += (size_t)bs * MOM_ROW;
-    return b;
+    return (size_t)slots * per + 160 * 8;
 }
+
+// spawn kernel: three 32-bit words per table entry (unit offset, count word,
+// permutation) and the scratch words
+size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8; }
 
 constexpr size_t LDS_MAX = 160 * 1024;
 
 struct Resolved {
-    int W, nb, B, log2B, slots, block;
-    i64 cap_t, cap_s, dump_cap;
+    int W, nb, B, log2B, slots, block, two_pass, log2G, log2SUB;
+    i64 cap_t, cap_s, cap_c, dump_cap;
     size_t off_ctrl, off_inst, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
-        off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], total;
+        off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], off_coarse,
+        off_coarse_n, total;
     int nsq;
 };
 
@@ -241,14 +260,15 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     if (L.block == 0) L.block = h->model == FQ_MOM1D ? 512 : 1024;
     if (L.block != 256 && L.block != 512 && L.block != 1024) { err = "block must be 256, 512 or 1024"; return FQ_EINVAL; }
     if (L.lds_slots > 8 * L.block) { err = "lds_slots must be <= 8 * block"; return FQ_EINVAL; }
-    if (lds_bytes(R.W, h->model, L.lds_slots, L.block) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
+    if (lds_bytes(R.W, L.lds_slots) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
     if (L.buckets == 0) {
         double uniq = (double)L.table_capacity + 0.25 * (double)L.spawn_capacity;
         i64 b = (i64)std::ceil(uniq / (0.55 * L.lds_slots));
         L.buckets = (int)((i64)1 << ilog2(std::max<i64>(b, 1)));
     }
-    if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > (1 << 22)) {
-        err = "buckets must be a power of two <= 2^22";
+    if (L.buckets > 16384) L.buckets = 16384;
+    if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > 16384) {
+        err = "buckets must be a power of two <= 16384";
         return FQ_EINVAL;
     }
     R.B = L.buckets;
@@ -261,6 +281,12 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     };
     R.cap_t = std::min<i64>(cap((double)L.table_capacity / R.B), R.slots);
     R.cap_s = cap((double)L.spawn_capacity / R.B);
+    // spawn partition: one pass into the buckets for B <= 64, otherwise G
+    // coarse groups (B/G <= 256 buckets each) with 64 sub-slabs per group
+    R.two_pass = R.B > 64;
+    R.log2G = R.two_pass ? std::min(6, std::max(4, R.log2B - 8)) : R.log2B;
+    R.log2SUB = 6;
+    R.cap_c = R.two_pass ? cap((double)L.spawn_capacity / (double)((i64)1 << (R.log2G + R.log2SUB))) + 256 : 1;
     R.dump_cap = (p->flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) ? L.spawn_capacity + L.table_capacity : 0;
     R.nsq = (h->N + 2) * (h->N + 2) + 8;
     size_t o = 0;
@@ -287,6 +313,8 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
         R.off_slab[q] = take(rec_bytes(R.W) * (size_t)R.B * R.cap_s);
         R.off_slab_n[q] = take(sizeof(int) * R.B);
     }
+    R.off_coarse = take(rec_bytes(R.W) * (size_t)R.cap_c << (R.log2G + R.log2SUB));
+    R.off_coarse_n = take(sizeof(int) << (R.log2G + R.log2SUB));
     const i64 dc = std::max<i64>(R.dump_cap, 1);
     R.off_dsp_parent = take(sizeof(u64) * R.W * dc);
     R.off_dsp_attempt = take(sizeof(i64) * dc);
@@ -315,7 +343,7 @@ struct fq_handle {
     int parity;
     std::string err;
     int timing;
-    double time_ms;
+    double time_ms[3];
     i64 launches;
     std::vector<hipEvent_t> ev;
     std::vector<StepStats> ring_host;
@@ -464,6 +492,12 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     I.dmg_val = (double *)(q->ws + R.off_dmg_val);
     I.dump_cap = R.dump_cap;
     I.part = (Part *)(q->ws + R.off_part);
+    I.two_pass = R.two_pass;
+    I.log2G = R.log2G;
+    I.log2SUB = R.log2SUB;
+    I.cap_c = R.cap_c;
+    I.coarse = q->ws + R.off_coarse;
+    I.coarse_n = (int *)(q->ws + R.off_coarse_n);
     I.spart[0] = (SpawnPart *)(q->ws + R.off_spart[0]);
     I.spart[1] = (SpawnPart *)(q->ws + R.off_spart[1]);
     q->d_inst = (Inst *)(q->ws + R.off_inst);
@@ -473,15 +507,17 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
-    const void *kf = step_kernel(R.W, h->model, R.block);
-    size_t lb = lds_bytes(R.W, h->model, R.slots, R.block);
+    const void *km = step_kernel(R.W, variant(h->model, h->M), R.block, false);
+    const void *ks = step_kernel(R.W, variant(h->model, h->M), R.block, true);
     hipError_t e = hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl));
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: workspace initialisation"); delete q; return FQ_EHIP; }
-    e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb);
-    if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernel)"); delete q; return FQ_EHIP; }
+    e = hipFuncSetAttribute(km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(R.W, R.slots));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_spawn_bytes(R.cap_t));
+    if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
     q->ring_host.resize(RING);
     *out = q;
     return FQ_OK;
@@ -530,13 +566,33 @@ int fq_get_layout(const fq_handle *q, fq_layout *layout)
     return FQ_OK;
 }
 
-static int launch_step(fq_handle *q, int mode, hipStream_t s)
+static int launch_merge(fq_handle *q, hipStream_t s)
 {
     const Resolved &R = q->R;
-    const void *kf = step_kernel(R.W, q->h.model, R.block);
-    size_t lb = lds_bytes(R.W, q->h.model, R.slots, R.block);
+    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.block, false);
+    void *args[] = {(void *)&q->d_inst};
+    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lds_bytes(R.W, R.slots), s));
+    return FQ_OK;
+}
+
+// mode 0: spawns of the table the merge just wrote; mode 1: of a state that was set
+static int launch_spawn(fq_handle *q, int mode, hipStream_t s)
+{
+    const Resolved &R = q->R;
+    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.block, true);
     void *args[] = {(void *)&q->d_inst, (void *)&mode};
-    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lb, s));
+    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lds_spawn_bytes(R.cap_t), s));
+    return FQ_OK;
+}
+
+static int launch_partition(fq_handle *q, hipStream_t s)
+{
+    const Resolved &R = q->R;
+    if (!R.two_pass) return FQ_OK;
+    const int nblk = 1 << (R.log2G + R.log2SUB);
+    if (R.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(nblk), dim3(1024), 0, s, (const Inst *)q->d_inst);
+    else hipLaunchKernelGGL(k_part<2>, dim3(nblk), dim3(1024), 0, s, (const Inst *)q->d_inst);
+    HIPCHK(q, hipGetLastError());
     return FQ_OK;
 }
 
@@ -602,6 +658,7 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
         HIPCHK(q, hipMemsetAsync(q->inst.tab_n[k], 0, sizeof(int) * R.B, s));
         HIPCHK(q, hipMemsetAsync(q->inst.slab_n[k], 0, sizeof(int) * R.B, s));
     }
+    HIPCHK(q, hipMemsetAsync(q->inst.coarse_n, 0, sizeof(int) << (R.log2G + R.log2SUB), s));
     // stage entries in the parity-1 slab, insert into table[0]
     u64 *sa = (u64 *)q->inst.slab[1];
     double *sv = (double *)(q->inst.slab[1] + sizeof(u64) * W * n);
@@ -658,7 +715,9 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
     HIPCHK(q, hipMemcpy(q->inst.ref_off, off.data(), sizeof(int) * (R.B + 1), hipMemcpyHostToDevice));
     HIPCHK(q, hipMemcpy(q->d_inst, &q->inst, sizeof(Inst), hipMemcpyHostToDevice));
     // spawns of c^(step) for step+1
-    int rc = launch_step(q, 1, s);
+    int rc = launch_spawn(q, 1, s);
+    if (rc) return rc;
+    rc = launch_partition(q, s);
     if (rc) return rc;
     Ctrl cc;
     rc = read_ctrl(q, cc, s);
@@ -680,12 +739,16 @@ int fq_set_timing(fq_handle *q, int32_t enable)
     return FQ_OK;
 }
 
-int fq_kernel_time(fq_handle *q, double *ms, int64_t *launches, int32_t reset)
+int fq_kernel_time(fq_handle *q, double *ms, int32_t n, int64_t *steps, int32_t reset)
 {
-    if (!q) return FQ_EINVAL;
-    if (ms) *ms = q->time_ms;
-    if (launches) *launches = q->launches;
-    if (reset) { q->time_ms = 0; q->launches = 0; }
+    if (!q || (ms && n < 1)) return FQ_EINVAL;
+    for (int j = 0; ms && j < n && j < NEV - 1; j++) ms[j] = q->time_ms[j];
+    for (int j = NEV - 1; ms && j < n; j++) ms[j] = 0.0;
+    if (steps) *steps = q->launches;
+    if (reset) {
+        for (double &t : q->time_ms) t = 0;
+        q->launches = 0;
+    }
     return FQ_OK;
 }
 
@@ -702,27 +765,35 @@ int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream
     while (done < n_steps) {
         const i64 chunk = std::min<i64>(RING, n_steps - done);
         hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->ring_base, (i64)(q->step + 1));
-        if (q->timing && (i64)q->ev.size() < 2 * chunk) {
+        if (q->timing && (i64)q->ev.size() < NEV * chunk) {
             size_t old = q->ev.size();
-            q->ev.resize(2 * chunk);
+            q->ev.resize(NEV * chunk);
             for (size_t k = old; k < q->ev.size(); k++) HIPCHK(q, hipEventCreate(&q->ev[k]));
         }
         for (i64 k = 0; k < chunk; k++) {
-            if (q->timing) HIPCHK(q, hipEventRecord(q->ev[2 * k], s));
-            int rc = launch_step(q, 0, s);
+            hipEvent_t *ev = q->timing ? &q->ev[NEV * k] : nullptr;
+            if (ev) HIPCHK(q, hipEventRecord(ev[0], s));
+            int rc = launch_merge(q, s);
             if (rc) return rc;
-            if (q->timing) HIPCHK(q, hipEventRecord(q->ev[2 * k + 1], s));
+            if (ev) HIPCHK(q, hipEventRecord(ev[1], s));
+            rc = launch_spawn(q, 0, s);
+            if (rc) return rc;
+            if (ev) HIPCHK(q, hipEventRecord(ev[2], s));
+            rc = launch_partition(q, s);
+            if (rc) return rc;
             hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, (const Inst *)q->d_inst);
+            if (ev) HIPCHK(q, hipEventRecord(ev[3], s));
         }
         Ctrl c;
         int rc = read_ctrl(q, c, s);
         if (rc) return rc;
         if (q->timing) {
-            for (i64 k = 0; k < chunk; k++) {
-                float ms = 0;
-                HIPCHK(q, hipEventElapsedTime(&ms, q->ev[2 * k], q->ev[2 * k + 1]));
-                q->time_ms += ms;
-            }
+            for (i64 k = 0; k < chunk; k++)
+                for (int j = 0; j < NEV - 1; j++) {
+                    float ms = 0;
+                    HIPCHK(q, hipEventElapsedTime(&ms, q->ev[NEV * k + j], q->ev[NEV * k + j + 1]));
+                    q->time_ms[j] += ms;
+                }
             q->launches += chunk;
         }
         const i64 completed = c.step - q->step;

@@ -24,7 +24,6 @@
 namespace fq {
 
 constexpr int MOM_MAXM = 32;     // largest M of the momentum model on the device
-constexpr int MOM_ROW = 100;     // bytes of per-thread LDS scratch (occ, start, list)
 
 struct ModelConst {
     int M, N, nb;
@@ -91,47 +90,54 @@ __device__ __forceinline__ T real_entry(const ModelConst &C, T a, T st, int o, i
 
 // ---------------------------------------------------------------- momentum
 
-struct MomRow {
-    unsigned char *occ, *start, *list;
+// A momentum-space parent decoded into registers.  Occupied modes are the
+// runs of ones of the address: `st` marks the first bit of every run, the
+// mode of a run starting at bit s is the number of zeros below s, and the
+// run of mode j starts after the j-th zero (`z` = zeros inside the N+M-1
+// bits).  Everything is bit arithmetic on one or two words.
+template <class T> struct MomP {
+    T a, st, z;
     int o, o_odd, dbl;
 };
 
-__device__ __forceinline__ MomRow mom_row(unsigned char *base)
+template <class T> __device__ __forceinline__ int mom_mode_at(const MomP<T> &P, int s)
 {
-    MomRow r;
-    r.occ = base;
-    r.start = base + MOM_MAXM;
-    r.list = base + 2 * MOM_MAXM;
-    r.o = r.o_odd = r.dbl = 0;
-    return r;
+    return s - popc(P.a & mask_below<T>(s));
+}
+template <class T> __device__ __forceinline__ int mom_start(const MomP<T> &P, int j)
+{
+    return j == 0 ? 0 : select(P.z, j - 1) + 1;
 }
 
-template <class T> __device__ __forceinline__ void mom_decode(const ModelConst &C, T a, MomRow &R)
+template <class T> __device__ __forceinline__ MomP<T> mom_parent(const ModelConst &C, T a)
 {
-    int pos = 0, o = 0, oo = 0, dbl = 0;
-    for (int j = 0; j < C.M; j++) {
-        int n = runlen(a, pos);
-        R.occ[j] = (unsigned char)n;
-        R.start[j] = (unsigned char)pos;
-        if (n) {
-            R.list[o++] = (unsigned char)j;
-            oo += j & 1;
-            dbl += n >= 2;
-        }
-        pos += n + 1;
+    MomP<T> P;
+    P.a = a;
+    P.st = run_starts(a);
+    P.z = ~a & mask_below<T>(C.nb);
+    P.o = popc(P.st);
+    P.dbl = popc(P.st & shr(a, 1));  // runs of length >= 2
+    int oo = 0;
+    T x = P.st;
+    while (!is_zero(x)) {
+        int s = ctz(x);
+        x = x & ~one_at<T>(s);
+        oo += mom_mode_at(P, s) & 1;
     }
-    R.o = o;
-    R.o_odd = oo;
-    R.dbl = dbl;
+    P.o_odd = oo;
+    return P;
 }
 
-__device__ __forceinline__ double mom_diag(const ModelConst &C, const MomRow &R)
+template <class T> __device__ __forceinline__ double mom_diag(const ModelConst &C, const MomP<T> &P)
 {
     double kin = 0.0;
     i64 sq = 0;
-    for (int j = 0; j < C.M; j++) {
-        int n = R.occ[j];
-        if (n > 0) kin = kin + C.eps[j] * (double)n;
+    T x = P.st;
+    while (!is_zero(x)) {  // occupied modes in ascending order
+        int s = ctz(x);
+        x = x & ~one_at<T>(s);
+        int n = runlen(P.a, s);
+        kin = kin + C.eps[mom_mode_at(P, s)] * (double)n;
         sq += (i64)n * n;
     }
     i64 N = C.N;
@@ -144,14 +150,19 @@ __device__ __forceinline__ int mom_R(int K, int M)
 {
     return (M & 1) ? (M - 1) / 2 : ((K & 1) ? M / 2 - 1 : M / 2);
 }
-__device__ __forceinline__ int mom_npairs(const MomRow &R) { return R.o * (R.o - 1) / 2 + R.dbl; }
+__device__ __forceinline__ int mod_add(int x, int y, int M)
+{
+    int r = x + y;
+    return r >= M ? r - M : r;
+}
+template <class T> __device__ __forceinline__ int mom_npairs(const MomP<T> &P) { return P.o * (P.o - 1) / 2 + P.dbl; }
 // column size: sum over pairs of R(K); for even M, pairs of odd K are the
 // distinct pairs of one odd and one even mode
-__device__ __forceinline__ i64 mom_m(const MomRow &R, int M)
+template <class T> __device__ __forceinline__ i64 mom_m(const MomP<T> &P, int M)
 {
-    i64 P = mom_npairs(R);
-    if (M & 1) return P * ((M - 1) / 2);
-    return P * (M / 2) - (i64)R.o_odd * (R.o - R.o_odd);
+    i64 np = mom_npairs(P);
+    if (M & 1) return np * ((M - 1) / 2);
+    return np * (M / 2) - (i64)P.o_odd * (P.o - P.o_odd);
 }
 
 template <class T> __device__ __forceinline__ T del_bit(T a, int x)
@@ -163,78 +174,234 @@ template <class T> __device__ __forceinline__ T ins_one(T a, int x)
     return (a & mask_below<T>(x)) | one_at<T>(x) | shl(shr(a, x), x + 1);
 }
 
-// move {p,q} -> {r,s} (p <= q, r <= s, disjoint): value and destination
+// move {p,q} -> {r,s} (p <= q modes starting at bits sp <= sq; r <= s): value
+// and destination
 template <class T>
-__device__ __forceinline__ T mom_move(const ModelConst &C, T a, const MomRow &R, int p, int q, int di,
+__device__ __forceinline__ T mom_move(const ModelConst &C, const MomP<T> &P, int p, int q, int sp, int sq, int di,
                                       double &h)
 {
     const int M = C.M;
-    int K = (p + q) % M;
+    int K = mod_add(p, q, M);
     int half = K / 2;
     int idxp = p <= half ? p : half + 1 + (p - K - 1);
     int idx = di < idxp ? di : di + 1;
     int r = idx <= half ? idx : K + 1 + (idx - half - 1);
-    int s = (K - r + M) % M;
-    int np = R.occ[p], nq = R.occ[q], nr = R.occ[r], ns = R.occ[s];
+    int s = K - r;
+    if (s < 0) s += M;
+    const int sr = mom_start(P, r), ss = mom_start(P, s);
+    int np = runlen(P.a, sp), nq = runlen(P.a, sq), nr = runlen(P.a, sr), ns = runlen(P.a, ss);
     int A = np * (nq - (p == q ? 1 : 0));
     int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
     int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);
     h = (C.coef * (double)cc) * (C.sq[A] * C.sq[B]);
     // four single-bit edits applied from the highest position down, so each
     // edit leaves the positions of the lower ones valid
-    int pp = R.start[p], pq = R.start[q], pr = R.start[r], ps = R.start[s];
-    // removals at pq >= pp, insertions at ps >= pr; merge descending
-    int rem[2] = {pq, pp}, ins[2] = {ps, pr};
-    int ir = 0, ii = 0;
-    T d = a;
+    int rem0 = sq, rem1 = sp, ins0 = ss, ins1 = sr;  // each pair descending
+    T d = P.a;
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-        bool take_ins = ir >= 2 || (ii < 2 && ins[ii] > rem[ir]);
-        if (take_ins) { d = ins_one(d, ins[ii]); ii++; }
-        else { d = del_bit(d, rem[ir]); ir++; }
+        bool take_ins = rem0 < 0 || (ins0 >= 0 && ins0 > rem0);
+        if (take_ins) { d = ins_one(d, ins0); ins0 = ins1; ins1 = -1; }
+        else { d = del_bit(d, rem0); rem0 = rem1; rem1 = -1; }
     }
     return d;
 }
 
-// pair index -> (p, q) in the canonical pair order
-__device__ __forceinline__ void mom_pair(const MomRow &R, int pi, int &p, int &q)
+// pair index -> (p, q) in the canonical pair order: occupied p ascending,
+// then (p, p) when n_p >= 2, then (p, q) for occupied q > p
+template <class T>
+__device__ __forceinline__ void mom_pair(const MomP<T> &P, int pi, int &p, int &q, int &sp, int &sq)
 {
-    const int o = R.o;
-    for (int a = 0; a < o; a++) {
-        int pa = R.list[a];
-        int d = R.occ[pa] >= 2 ? 1 : 0;
-        int cnt = o - a - 1 + d;
+    T x = P.st;
+    int rank = 0;
+    while (!is_zero(x)) {
+        const int s = ctz(x);
+        x = x & ~one_at<T>(s);
+        const int d = is_zero(P.a & one_at<T>(s + 1)) ? 0 : 1;
+        const int cnt = P.o - rank - 1 + d;
         if (pi < cnt) {
-            p = pa;
-            if (d) q = pi == 0 ? pa : R.list[a + pi];
-            else q = R.list[a + 1 + pi];
+            sp = s;
+            p = mom_mode_at(P, s);
+            if (d && pi == 0) { sq = s; q = p; return; }
+            sq = select(P.st, rank + 1 + (pi - d));
+            q = mom_mode_at(P, sq);
             return;
         }
         pi -= cnt;
+        rank++;
     }
-    p = q = R.list[0];  // not reached for valid pi
+    p = q = sp = sq = 0;  // not reached for valid pi
 }
 
-// column entry e -> (p, q, di) by walking pairs in canonical order
-__device__ __forceinline__ void mom_entry(const MomRow &R, int M, i64 e, int &p, int &q, int &di)
+// iterator over the column entries of a momentum-space parent in canonical
+// order; rows are skipped with closed-form row sizes
+template <class T> struct PairIt {
+    T xa, xb;               // remaining run starts for the row index / partner
+    int sa, pa, sb, pb;     // current pair: bit starts and modes
+    int di, Rk;
+};
+
+template <class T>
+__device__ __forceinline__ bool mom_it_row(const MomP<T> &P, int M, PairIt<T> &it)
 {
-    const int o = R.o;
-    for (int a = 0; a < o; a++) {
-        int pa = R.list[a];
-        if (R.occ[pa] >= 2) {
-            int Rk = mom_R((2 * pa) % M, M);
-            if (e < Rk) { p = q = pa; di = (int)e; return; }
-            e -= Rk;
+    // position the iterator on the first pair of row it.sa (already set)
+    if (!is_zero(P.a & one_at<T>(it.sa + 1))) {  // (p, p)
+        it.sb = it.sa;
+        it.pb = it.pa;
+        it.Rk = mom_R(mod_add(it.pa, it.pa, M), M);
+        it.xb = it.xa;
+        return true;
+    }
+    if (is_zero(it.xa)) return false;
+    it.sb = ctz(it.xa);
+    it.xb = it.xa & ~one_at<T>(it.sb);
+    it.pb = mom_mode_at(P, it.sb);
+    it.Rk = mom_R(mod_add(it.pa, it.pb, M), M);
+    return true;
+}
+
+template <class T>
+__device__ __forceinline__ void mom_it_init(const MomP<T> &P, int M, i64 e, PairIt<T> &it)
+{
+    T x = P.st;
+    int rank = 0, odd_seen = 0;
+    while (!is_zero(x)) {
+        const int s = ctz(x);
+        x = x & ~one_at<T>(s);
+        const int pm = mom_mode_at(P, s);
+        const int d = is_zero(P.a & one_at<T>(s + 1)) ? 0 : 1;
+        const i64 pairs = P.o - rank - 1 + d;
+        i64 row;
+        if (M & 1) {
+            row = pairs * ((M - 1) / 2);
+        } else {
+            const int odd_after = P.o_odd - odd_seen - (pm & 1);
+            const int even_after = (P.o - rank - 1) - odd_after;
+            row = pairs * (M / 2) - (i64)((pm & 1) ? even_after : odd_after);
         }
-        for (int b = a + 1; b < o; b++) {
-            int qb = R.list[b];
-            int Rk = mom_R((pa + qb) % M, M);
-            if (e < Rk) { p = pa; q = qb; di = (int)e; return; }
-            e -= Rk;
+        if (e < row) {
+            it.sa = s;
+            it.pa = pm;
+            it.xa = x;
+            mom_it_row(P, M, it);
+            while (e >= it.Rk) {
+                e -= it.Rk;
+                it.sb = ctz(it.xb);
+                it.xb = it.xb & ~one_at<T>(it.sb);
+                it.pb = mom_mode_at(P, it.sb);
+                it.Rk = mom_R(mod_add(it.pa, it.pb, M), M);
+            }
+            it.di = (int)e;
+            return;
+        }
+        e -= row;
+        odd_seen += pm & 1;
+        rank++;
+    }
+    it.sa = it.sb = it.pa = it.pb = 0;
+    it.di = 0;
+    it.Rk = 1;
+}
+
+template <class T> __device__ __forceinline__ void mom_it_next(const MomP<T> &P, int M, PairIt<T> &it)
+{
+    if (++it.di < it.Rk) return;
+    it.di = 0;
+    if (!is_zero(it.xb)) {
+        it.sb = ctz(it.xb);
+        it.xb = it.xb & ~one_at<T>(it.sb);
+        it.pb = mom_mode_at(P, it.sb);
+        it.Rk = mom_R(mod_add(it.pa, it.pb, M), M);
+        return;
+    }
+    while (!is_zero(it.xa)) {  // next row
+        it.sa = ctz(it.xa);
+        it.xa = it.xa & ~one_at<T>(it.sa);
+        it.pa = mom_mode_at(P, it.sa);
+        if (mom_it_row(P, M, it)) return;
+    }
+    it.Rk = 1;  // past the end (not used)
+}
+
+// A momentum-space parent with the start bit of every mode packed into
+// registers (byte j of pos = first bit of the run of mode j, byte M = N+M), so
+// a destination's occupation and position cost a few instructions.  MAXM is
+// the compile-time bound on M.
+template <class T, int MAXM> struct MomD {
+    static constexpr int NW = MAXM / 8 + 1;
+    MomP<T> P;
+    u64 pos[NW];
+};
+
+template <int NW> __device__ __forceinline__ int byte_at(const u64 *w, int j)
+{
+    u64 x = w[0];
+#pragma unroll
+    for (int k = 1; k < NW; k++) x = j >= 8 * k ? w[k] : x;
+    return (int)((x >> ((j & 7) * 8)) & 0xffull);
+}
+
+template <class T, int MAXM> __device__ __forceinline__ MomD<T, MAXM> mom_decode_packed(const ModelConst &C, T a)
+{
+    MomD<T, MAXM> D;
+    D.P.a = a;
+    D.P.st = run_starts(a);
+    D.P.z = ~a & mask_below<T>(C.nb);
+    D.P.o = popc(D.P.st);
+    D.P.dbl = popc(D.P.st & shr(a, 1));
+#pragma unroll
+    for (int w = 0; w < MomD<T, MAXM>::NW; w++) D.pos[w] = 0;
+    T zz = D.P.z | one_at<T>(C.nb);  // separators plus a virtual one after the last mode
+    int prev = 0, oo = 0;
+#pragma unroll
+    for (int j = 1; j <= MAXM; j++) {
+        if (j <= C.M) {
+            const int z0 = ctz(zz);
+            zz = zz & ~one_at<T>(z0);
+            const int sj = z0 + 1;
+            oo += ((j - 1) & 1) & (sj - prev - 1 > 0 ? 1 : 0);
+            D.pos[j >> 3] |= (u64)sj << ((j & 7) * 8);
+            prev = sj;
         }
     }
-    p = q = R.list[0];
-    di = 0;
+    D.P.o_odd = oo;
+    return D;
+}
+
+template <class T, int MAXM> __device__ __forceinline__ int mom_pos(const MomD<T, MAXM> &D, int j)
+{
+    return byte_at<MomD<T, MAXM>::NW>(D.pos, j);
+}
+
+// move {p,q} -> {r,s} using the packed start positions
+template <class T, int MAXM>
+__device__ __forceinline__ T mom_move_d(const ModelConst &C, const MomD<T, MAXM> &D, int p, int q, int sp, int sq,
+                                        int di, double &h)
+{
+    const int M = C.M;
+    int K = mod_add(p, q, M);
+    int half = K / 2;
+    int idxp = p <= half ? p : half + 1 + (p - K - 1);
+    int idx = di < idxp ? di : di + 1;
+    int r = idx <= half ? idx : K + 1 + (idx - half - 1);
+    int s = K - r;
+    if (s < 0) s += M;
+    const int sr = mom_pos(D, r), ss = mom_pos(D, s);
+    const int np = mom_pos(D, p + 1) - sp - 1, nq = mom_pos(D, q + 1) - sq - 1;
+    const int nr = mom_pos(D, r + 1) - sr - 1, ns = mom_pos(D, s + 1) - ss - 1;
+    int A = np * (nq - (p == q ? 1 : 0));
+    int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
+    int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);
+    h = (C.coef * (double)cc) * (C.sq[A] * C.sq[B]);
+    int rem0 = sq, rem1 = sp, ins0 = ss, ins1 = sr;
+    T d = D.P.a;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        bool take_ins = rem0 < 0 || (ins0 >= 0 && ins0 > rem0);
+        if (take_ins) { d = ins_one(d, ins0); ins0 = ins1; ins1 = -1; }
+        else { d = del_bit(d, rem0); rem0 = rem1; rem1 = -1; }
+    }
+    return d;
 }
 
 }  // namespace fq

@@ -19,10 +19,15 @@
 //   4. compact survivors into table[1-p] and into LDS;
 //   5. spawn for step n+2 from every survivor: exact columns when
 //      |c| >= t_rel m, else ceil|c| Philox picks; attempts are expanded over
-//      the workgroup by a prefix sum over 4-attempt units and scattered to
-//      the destination buckets of slab[1-p] (atomic slot allocation).
-// The last workgroup to finish (completion counter) performs the shift
-// update (Eq. shift-update), writes the statistics row and resets counters.
+//      the workgroup by a prefix sum over 4-attempt units.  Records are
+//      partitioned in rounds: every thread generates one unit into
+//      registers, takes a rank inside its destination group with an LDS
+//      atomic, one global atomic per group reserves a contiguous run, and
+//      the records are stored into the runs.  With B <= 64 the groups are
+//      the buckets of slab[1-p]; otherwise they are G coarse groups and the
+//      partition kernel splits every group into its B/G buckets.
+// A separate one-workgroup kernel reduces the per-bucket partial statistics,
+// performs the shift update (Eq. shift-update) and writes the statistics row.
 #pragma once
 #include "fq_models.hpp"
 
@@ -49,7 +54,7 @@ struct Ctrl {
     u64 acc_norm[2];   // norm of a state being set (set_state only)
     i64 dump_spawn_n, dump_merged_n;
     i64 stop_step;     // batch: do not advance past this step
-    int err_bucket, pad0;
+    int err_bucket, spawn_par;  // spawn_par: parity of the slab being produced
     u64 phase[10];     // summed wall-clock ticks per phase (opt-in diagnostics)
     u64 probes;        // LDS hash probes summed over all inserts (diagnostics)
     u64 inserts;
@@ -94,6 +99,12 @@ struct Inst {
     i64 dump_cap;
     Part *part;          // [B]
     SpawnPart *spart[2]; // [row parity][B]
+    // two-pass spawn partition (B > 64): G = 2^log2G groups of B/G buckets,
+    // each with SUB = 2^log2SUB coarse sub-slabs of cap_c records
+    int two_pass, log2G, log2SUB, pad2;
+    i64 cap_c;
+    char *coarse;
+    int *coarse_n;
 };
 
 __device__ __forceinline__ void set_error(Ctrl *c, int code, int bucket)
@@ -179,7 +190,6 @@ struct Lds {
     u32 *state;     // W = 2 slot state: 0 empty, 1 busy, 2 full
     u64 *lo, *hi;   // fixed-point accumulators; later reused for survivors
     i64 *misc;      // scan scratch and block accumulators
-    unsigned char *rows;
     int mask;
 };
 
@@ -251,17 +261,12 @@ template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Ins
 // ---------------------------------------------------------------- spawn info
 
 template <int W, int MODEL>
-__device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T a, double c,
-                                           unsigned char *row, u32 &cnt, bool &exact, int &bad)
+__device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T a, double c, u32 &cnt, bool &exact,
+                                           int &bad)
 {
     i64 m;
-    if (MODEL == 0) {
-        m = 2 * popc(run_starts(a));
-    } else {
-        MomRow R = mom_row(row);
-        mom_decode(I.mc, a, R);
-        m = mom_m(R, I.mc.M);
-    }
+    if (MODEL == 0) m = 2 * popc(run_starts(a));
+    else m = mom_m(mom_parent(I.mc, a), I.mc.M);
     double ac = fabs(c);
     exact = (m == 0) || ac >= I.t_rel * (double)m;
     if (exact) {
@@ -273,10 +278,196 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
     }
 }
 
+// ---------------------------------------------------------------- spawn walk
+
+// Spawn records of the units [u_lo, u_hi) (all exact or all stochastic).
+// Blocked assignment: thread t walks a contiguous range of units in order, so
+// a parent is decoded once and an exact-column iterator carries over between
+// its units.  Records are partitioned in rounds: one unit per thread into
+// registers, a rank inside the destination group from an LDS atomic, one
+// global atomic per group reserving a contiguous run, then the stores.
+template <int W, int MODEL, int BS, bool EXACT>
+__device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const int b, const int out_par,
+                                            const u32 spawn_step, const int nS, const u32 *info, const u32 *perm,
+                                            const int in_par, const i64 u_lo, const i64 u_hi)
+{
+    typedef typename AddrOf<W>::T T;
+    constexpr int MAXM = MODEL == 1 ? 16 : 32;
+    const int tid = threadIdx.x;
+    Ctrl *ctrl = I.ctrl;
+    const int log2G = I.two_pass ? I.log2G : I.log2B;
+    const int G = 1 << log2G;
+    const int gshift = I.log2B - log2G;
+    const int sub = (int)(blockIdx.x & ((1u << I.log2SUB) - 1));
+    int *gcnt = (int *)(L.misc + 64);  // G <= 64 counters
+    i64 *gbase = L.misc + 96;          // G <= 64 run bases
+    const double dtau = I.dtau;
+    if (b == 0 && tid == 0) ctrl->spawn_par = out_par;
+    const i64 nu = u_hi - u_lo;
+    if (nu <= 0) return;
+    const i64 u_beg = u_lo + nu * tid / BS, u_end = u_lo + nu * (tid + 1) / BS;
+    const i64 rounds = (nu + BS - 1) / BS;
+    i64 u = u_beg;
+    int cur = -1;     // current parent
+    i64 cur_end = 0;  // first unit of the next parent
+    i64 cur_off = 0;
+    u32 cnt = 0;
+    double c = 0.0, qd = 0.0;
+    u64 a0 = 0, a1 = 0;
+    T st;
+    int o = 0, np = 0;
+    MomD<T, MAXM> D;
+    PairIt<T> it;
+    for (i64 rr = 0; rr < rounds; rr++) {
+        if (tid < G) gcnt[tid] = 0;
+        __syncthreads();
+        T d0, d1, d2, d3;
+        double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+        int nk = 0;
+        u32 k0 = 0;
+        if (u < u_end) {
+            if (u >= cur_end) {
+                // parent holding unit u: binary search first, then walk forward
+                int i;
+                if (cur < 0) {
+                    int lo_i = 0, hi_i = nS - 1;
+                    while (lo_i < hi_i) {
+                        int mid = (lo_i + hi_i + 1) >> 1;
+                        if ((i64)info[2 * mid] <= u) lo_i = mid; else hi_i = mid - 1;
+                    }
+                    i = lo_i;
+                } else {
+                    i = cur + 1;
+                    while (i + 1 < nS && (i64)info[2 * (i + 1)] <= u) i++;
+                }
+                cur = i;
+                cur_off = info[2 * i];
+                cur_end = i + 1 < nS ? (i64)info[2 * (i + 1)] : u_hi;
+                cnt = info[2 * i + 1] & 0x7fffffffu;
+                const i64 e = (i64)b * I.cap_t + perm[i];
+                a0 = I.tab_a[in_par][0][e];
+                a1 = W == 2 ? I.tab_a[in_par][1][e] : 0;
+                c = I.tab_v[in_par][e];
+                const T a = AddrOf<W>::make(a0, a1);
+                if (MODEL == 0) {
+                    st = run_starts(a);
+                    o = popc(st);
+                    if (!EXACT) qd = (double)(2 * o) / (double)cnt;
+                } else {
+                    D = mom_decode_packed<T, MAXM>(I.mc, a);
+                    np = mom_npairs(D.P);
+                    if (EXACT) mom_it_init(D.P, I.mc.M, (i64)(4 * (u - cur_off)), it);
+                }
+            }
+            const u32 qu = (u32)(u - cur_off);
+            k0 = 4 * qu;
+            nk = (int)min(cnt - k0, 4u);
+            if (MODEL == 0) {
+                const T a = AddrOf<W>::make(a0, a1);
+                const u32 m = 2 * o;
+                R4 r = {0, 0, 0, 0};
+                if (!EXACT) r = draw(I.seed, a0, a1, spawn_step, 0u, qu);
+                auto gen = [&](int e, T &dd, double &vv) {
+                    int idx = EXACT ? (int)(k0 + e) : (int)pick(rword(r, e), m);
+                    double h;
+                    dd = real_entry(I.mc, a, st, o, idx, h);
+                    vv = (-(dtau * h)) * c;
+                    if (!EXACT) vv = vv * qd;
+                };
+                gen(0, d0, v0);
+                if (nk > 1) gen(1, d1, v1);
+                if (nk > 2) gen(2, d2, v2);
+                if (nk > 3) gen(3, d3, v3);
+            } else {
+                const int M = I.mc.M;
+                if (EXACT) {
+                    auto gen = [&](T &dd, double &vv) {
+                        double h;
+                        dd = mom_move_d(I.mc, D, it.pa, it.pb, it.sa, it.sb, it.di, h);
+                        vv = (-(dtau * h)) * c;
+                        mom_it_next(D.P, M, it);
+                    };
+                    gen(d0, v0);
+                    if (nk > 1) gen(d1, v1);
+                    if (nk > 2) gen(d2, v2);
+                    if (nk > 3) gen(d3, v3);
+                } else {
+                    const double cnt_d = (double)cnt;
+                    auto gen = [&](u32 w0, u32 w1, T &dd, double &vv) {
+                        int pp, qq, sp, sq;
+                        mom_pair(D.P, (int)pick(w0, (u32)np), pp, qq, sp, sq);
+                        const int Rk = mom_R(mod_add(pp, qq, M), M);
+                        const int di = (int)pick(w1, (u32)Rk);
+                        double h;
+                        dd = mom_move_d(I.mc, D, pp, qq, sp, sq, di, h);
+                        const double qn = (double)((i64)np * Rk) / cnt_d;
+                        vv = ((-(dtau * h)) * c) * qn;
+                    };
+                    R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k0 >> 1);
+                    gen(r.x, r.y, d0, v0);
+                    if (nk > 1) gen(r.z, r.w, d1, v1);
+                    if (nk > 2) {
+                        r = draw(I.seed, a0, a1, spawn_step, 0u, (k0 >> 1) + 1);
+                        gen(r.x, r.y, d2, v2);
+                        if (nk > 3) gen(r.z, r.w, d3, v3);
+                    }
+                }
+            }
+            u++;
+        }
+        // ranks inside the destination groups
+        int g0 = 0, g1 = 0, g2 = 0, g3 = 0, rk0 = 0, rk1 = 0, rk2 = 0, rk3 = 0;
+        if (nk > 0) { g0 = (int)(bucket_of(addr_hash(d0), I.log2B) >> gshift); rk0 = atomicAdd(&gcnt[g0], 1); }
+        if (nk > 1) { g1 = (int)(bucket_of(addr_hash(d1), I.log2B) >> gshift); rk1 = atomicAdd(&gcnt[g1], 1); }
+        if (nk > 2) { g2 = (int)(bucket_of(addr_hash(d2), I.log2B) >> gshift); rk2 = atomicAdd(&gcnt[g2], 1); }
+        if (nk > 3) { g3 = (int)(bucket_of(addr_hash(d3), I.log2B) >> gshift); rk3 = atomicAdd(&gcnt[g3], 1); }
+        __syncthreads();
+        // one reservation per group and round
+        if (tid < G) {
+            const int cg = gcnt[tid];
+            int *cn = I.two_pass ? &I.coarse_n[(tid << I.log2SUB) + sub] : &I.slab_n[out_par][tid];
+            gbase[tid] = cg ? (i64)atomicAdd(cn, cg) : 0;
+        }
+        __syncthreads();
+        auto put = [&](int g, int rk, const T &dd, double vv, u32 k) {
+            const i64 pos = gbase[g] + rk;
+            if (I.two_pass) {
+                const i64 cs = ((i64)g << I.log2SUB) + sub;
+                if (pos < I.cap_c) store_rec<W>(I.coarse, cs * I.cap_c + pos, dd, vv);
+                else set_error(ctrl, FQE_CAP_SLAB, g);
+            } else {
+                if (pos < I.cap_s) store_rec<W>(I.slab[out_par], (i64)g * I.cap_s + pos, dd, vv);
+                else set_error(ctrl, FQE_CAP_SLAB, g);
+            }
+            if (I.flags & 1) {
+                i64 di = atomicAdd((unsigned long long *)&ctrl->dump_spawn_n, 1ull);
+                if (di < I.dump_cap) {
+                    I.dsp_parent[di * W] = a0;
+                    if (W == 2) I.dsp_parent[di * W + 1] = a1;
+                    I.dsp_attempt[di] = (i64)k;
+                    I.dsp_dest[di * W] = word0(dd);
+                    if (W == 2) I.dsp_dest[di * W + 1] = word1(dd);
+                    I.dsp_val[di] = vv;
+                }
+            }
+        };
+        if (nk > 0) put(g0, rk0, d0, v0, k0);
+        if (nk > 1) put(g1, rk1, d1, v1, k0 + 1);
+        if (nk > 2) put(g2, rk2, d2, v2, k0 + 2);
+        if (nk > 3) put(g3, rk3, d3, v3, k0 + 3);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- the step
 
+// Merge of bucket b for step n+1: the diagonal survivors of table[p] and the
+// spawn records of slab[p] are summed per address in an LDS hash table, the
+// sums are compressed, the projected-energy terms of the bucket's reference
+// entries are accumulated, and the survivors are written to table[1-p]
+// together with the bucket's partial statistics.
 template <int W, int MODEL, int BS>
-__device__ void process_bucket(const Inst &I, const int b, const int mode, char *smem)
+__device__ void merge_bucket(const Inst &I, const int b, char *smem)
 {
     typedef typename AddrOf<W>::T T;
     const int tid = threadIdx.x;
@@ -300,10 +491,8 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
     L.lo = (u64 *)q; q += (size_t)slots * 8;
     L.hi = (u64 *)q; q += (size_t)slots * 8;
     L.state = (u32 *)q; if (W == 2) q += (size_t)slots * 4;
-    L.misc = (i64 *)q; q += 64 * 8;
-    L.rows = (unsigned char *)q;
+    L.misc = (i64 *)q; q += 160 * 8;
     L.mask = slots - 1;
-    unsigned char *myrow = L.rows + (size_t)tid * MOM_ROW;
 
     const bool timing = (I.flags & 4) != 0;
     u64 tprev = timing ? wall_clock64() : 0;
@@ -314,13 +503,18 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             tprev = t;
         }
     };
-    int nprobe = 0;
-    const int out_par = mode == 0 ? 1 - p : p;
-    const u32 spawn_step = (u32)(mode == 0 ? n + 2 : n + 1);
-    int nS = 0;  // survivors held in LDS for the spawn phase
+    const int out_par = 1 - p;
+    const int spt = slots / BS;  // candidate slots per thread (contiguous), <= 8
 
-    if (mode == 0) {
+    // candidate survivors of this thread: address words and value (0 = none)
+    u64 r0[8], r1[8];
+    double rc[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) { r0[k] = 0; r1[k] = 0; rc[k] = 0.0; }
+
+    {
         // ------------------------------------------------ 1. merge
+        int nprobe = 0;
         for (int s = tid; s < slots; s += BS) {
             L.k0[s] = EMPTY;
             if (W == 2) { L.k1[s] = EMPTY; L.state[s] = 0u; }
@@ -339,18 +533,27 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             T a = AddrOf<W>::make(a0, a1);
             double hii;
             if (MODEL == 0) hii = real_diag(I.mc, a);
-            else { MomRow R = mom_row(myrow); mom_decode(I.mc, a, R); hii = mom_diag(I.mc, R); }
+            else hii = mom_diag(I.mc, mom_parent(I.mc, a));
             double g = 1.0 + I.dtau * (S - hii);
             lds_add<W>(L, I, a0, a1, c * g, b, nprobe);
         }
         if (timing) { __syncthreads(); mark(1); }
         const int ns = min(I.slab_n[p][b], (int)I.cap_s);
         const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)sizeof(Rec<W>);
-        for (int i = tid; i < ns; i += BS) {
-            u64 a0, a1;
-            double v;
-            load_rec<W>(sb, i, a0, a1, v);
-            lds_add<W>(L, I, a0, a1, v, b, nprobe);
+        for (int i0 = 0; i0 < ns; i0 += 4 * BS) {
+            // four independent record loads in flight per thread
+            u64 x0[4], x1[4];
+            double xv[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = i0 + e * BS + tid;
+                if (i < ns) load_rec<W>(sb, i, x0[e], x1[e], xv[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int i = i0 + e * BS + tid;
+                if (i < ns) lds_add<W>(L, I, x0[e], x1[e], xv[e], b, nprobe);
+            }
         }
         __syncthreads();
         mark(2);
@@ -367,11 +570,7 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
         }
 
         // ------------------------------------------------ 2. compress (per slot, owner thread)
-        const int spt = slots / BS;  // slots per thread (contiguous), <= 8
-        u64 r0[8], r1[8];
-        double rc[8];
-        int mine = 0, used = 0;
-        u64 nlo = 0, nhi = 0;  // fixed-point partial norm
+        int used = 0;
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (k >= spt) break;
@@ -403,24 +602,16 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
             r0[k] = a0;
             r1[k] = a1;
             rc[k] = cn;
-            if (cn != 0.0) {
-                mine++;
-                u64 lo, hi;
-                int ovf = 0;
-                to_fixed(fabs(cn), lo, hi, ovf);
-                add128(nlo, nhi, lo, hi);
-            }
         }
-        mark(3);
         // expose compressed values for the projected-energy lookups
 #pragma unroll
         for (int k = 0; k < 8; k++)
             if (k < spt) L.lo[tid * spt + k] = dbits(rc[k]);
+        mark(3);
+        if (tid == 0) { L.misc[42] = 0; L.misc[43] = 0; L.misc[44] = 0; L.misc[45] = 0; }
         __syncthreads();
 
         // ------------------------------------------------ 3. projected energy
-        if (tid == 0) { L.misc[42] = 0; L.misc[43] = 0; L.misc[44] = 0; L.misc[45] = 0; }
-        __syncthreads();
         {
             const int r_beg = I.ref_off[b], r_end = I.ref_off[b + 1];
             for (int e = r_beg + tid; e < r_end; e += BS) {
@@ -440,196 +631,215 @@ __device__ void process_bucket(const Inst &I, const int b, const int mode, char 
                 }
             }
         }
-        // occupancy statistic (largest number of distinct addresses in a bucket)
         {
             i64 tot;
-            i64 u = block_excl_scan<BS>(used, L.misc, tot);
-            (void)u;
+            block_excl_scan<BS>(used, L.misc, tot);
             if (tid == 0) L.misc[46] = tot;
         }
-        // ------------------------------------------------ 4. compact
-        i64 total;
-        i64 base = block_excl_scan<BS>(mine, L.misc, total);
-        if (total > I.cap_t) {
-            if (tid == 0) set_error(ctrl, FQE_CAP_TABLE, b);
-            return;
-        }
-        {
-            const i64 ob = (i64)b * I.cap_t;
-            int w = (int)base;
+    }
+
+    // ---------------------------------------------------- 4. compaction and partial statistics
+    int mine = 0;
+    u64 nlo = 0, nhi = 0;  // fixed-point partial norm
 #pragma unroll
-            for (int k = 0; k < 8; k++) {
-                if (k < spt && rc[k] != 0.0) {
-                    L.k0[w] = r0[k];
-                    if (W == 2) L.k1[w] = r1[k];
-                    L.lo[w] = dbits(rc[k]);
-                    I.tab_a[out_par][0][ob + w] = r0[k];
-                    if (W == 2) I.tab_a[out_par][1][ob + w] = r1[k];
-                    I.tab_v[out_par][ob + w] = rc[k];
-                    w++;
-                }
+    for (int k = 0; k < 8; k++) {
+        if (k < spt && rc[k] != 0.0) {
+            mine++;
+            u64 lo, hi;
+            int ovf = 0;
+            to_fixed(fabs(rc[k]), lo, hi, ovf);
+            add128(nlo, nhi, lo, hi);
+        }
+    }
+    i64 total;
+    const i64 base = block_excl_scan<BS>(mine, L.misc, total);
+    if (total > I.cap_t) {
+        if (tid == 0) set_error(ctrl, FQE_CAP_TABLE, b);
+        return;
+    }
+    {
+        const i64 ob = (i64)b * I.cap_t;
+        int w = (int)base;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            if (k < spt && rc[k] != 0.0) {
+                I.tab_a[out_par][0][ob + w] = r0[k];
+                if (W == 2) I.tab_a[out_par][1][ob + w] = r1[k];
+                I.tab_v[out_par][ob + w] = rc[k];
+                w++;
             }
         }
-        // block totals of len and norm
-        if (tid == 0) { L.misc[40] = 0; L.misc[41] = 0; }
-        __syncthreads();
-        if (nlo | nhi) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
-        __syncthreads();
-        if (tid == 0) {
-            I.tab_n[out_par][b] = (int)total;
-            Part pt;
-            pt.norm[0] = (u64)L.misc[40];
-            pt.norm[1] = (u64)L.misc[41];
-            pt.hproj[0] = (u64)L.misc[42];
-            pt.hproj[1] = (u64)L.misc[43];
-            pt.vproj[0] = (u64)L.misc[44];
-            pt.vproj[1] = (u64)L.misc[45];
-            pt.len = total;
-            pt.load = L.misc[46];
-            I.part[b] = pt;
+    }
+    if (tid == 0) { L.misc[40] = 0; L.misc[41] = 0; }
+    __syncthreads();
+    if (nlo | nhi) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
+    __syncthreads();
+    if (tid == 0) {
+        I.tab_n[out_par][b] = (int)total;
+        Part pt;
+        pt.norm[0] = (u64)L.misc[40];
+        pt.norm[1] = (u64)L.misc[41];
+        pt.hproj[0] = (u64)L.misc[42];
+        pt.hproj[1] = (u64)L.misc[43];
+        pt.vproj[0] = (u64)L.misc[44];
+        pt.vproj[1] = (u64)L.misc[45];
+        pt.len = total;
+        pt.load = L.misc[46];
+        I.part[b] = pt;
+    }
+    mark(4);
+}
+
+// ---------------------------------------------------------------- spawn kernel
+
+// Spawns of the entries of table[par] in bucket b for step spawn_step
+// (mode 0: the table just produced by the merge; mode 1: a state that was
+// set).  Per entry the attempt count is computed (m exact entries when
+// |c| >= t_rel m, else ceil|c| picks); entries are ordered exact first by an
+// index permutation so that waves run one kind of unit; units of 4 attempts
+// are scanned and walked by spawn_units.
+template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *smem)
+{
+    typedef typename AddrOf<W>::T T;
+    const int tid = threadIdx.x;
+    Ctrl *ctrl = I.ctrl;
+    __shared__ int s_err;
+    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_err) return;
+    const i64 n = ctrl->step;
+    const int p = ctrl->parity;
+    // mode 0 runs after the merge of step n+1 (state in table[1-p]), mode 1 on c^(n)
+    const int par = mode == 0 ? 1 - p : p;
+    const u32 spawn_step = (u32)(mode == 0 ? n + 2 : n + 1);
+    Lds L;
+    L.misc = (i64 *)smem;
+    const bool timing = (I.flags & 4) != 0;
+    u64 tprev = timing ? wall_clock64() : 0;
+    auto mark = [&](int ph) {
+        if (timing && tid == 0) {
+            u64 t = wall_clock64();
+            atomicAdd((unsigned long long *)&ctrl->phase[ph], (unsigned long long)(t - tprev));
+            tprev = t;
         }
-        nS = (int)total;
-        mark(4);
-    } else {
-        // spawn-only pass: survivors are the stored entries of table[p]
-        nS = I.tab_n[p][b];
-        const i64 tb = (i64)b * I.cap_t;
-        for (int i = tid; i < nS; i += BS) {
-            L.k0[i] = I.tab_a[p][0][tb + i];
-            if (W == 2) L.k1[i] = I.tab_a[p][1][tb + i];
-            L.lo[i] = dbits(I.tab_v[p][tb + i]);
-        }
-        if (tid < 64) L.misc[tid] = 0;
+    };
+    // info[2 i] holds entry i's count word until the units are scanned, then
+    // unit offsets in exact-first order; info[2 w + 1] the count word of the
+    // w-th entry in that order and perm[w] its table index
+    u32 *info = (u32 *)(smem + 160 * 8);
+    u32 *perm = info + 2 * I.cap_t;
+    const int nS = I.tab_n[par][b];
+    const i64 tb = (i64)b * I.cap_t;
+    const int chunk = (nS + BS - 1) / BS;
+    const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
+    int n_ex = 0, bad = 0;
+    i64 nsp = 0;
+    for (int i = i0; i < i1; i++) {
+        const T a = AddrOf<W>::make(I.tab_a[par][0][tb + i], W == 2 ? I.tab_a[par][1][tb + i] : 0);
+        u32 cnt;
+        bool ex;
+        spawn_info<W, MODEL>(I, a, I.tab_v[par][tb + i], cnt, ex, bad);
+        info[2 * i] = cnt | (ex ? 0x80000000u : 0u);
+        nsp += cnt;
+        n_ex += ex ? 1 : 0;
+    }
+    if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
+    mark(5);
+    i64 tot_e, tot_sp;
+    i64 be = block_excl_scan<BS>(n_ex, L.misc, tot_e);
+    block_excl_scan<BS>(nsp, L.misc, tot_sp);
+    i64 bs_ = (i64)i0 - be;  // stochastic entries before this thread's chunk
+    for (int i = i0; i < i1; i++) {
+        const u32 ce = info[2 * i];
+        const int w = (ce >> 31) ? (int)be++ : (int)(tot_e + bs_++);
+        perm[w] = (u32)i;
+        info[2 * w + 1] = ce;
+    }
+    if (tid == 0) {
+        SpawnPart sp;
+        sp.exact = tot_e;
+        sp.inexact = nS - tot_e;
+        sp.spawns = tot_sp;
+        sp.pad = 0;
+        I.spart[spawn_step & 1][b] = sp;
     }
     __syncthreads();
-
-    // ---------------------------------------------------- 5. spawn
+    i64 utot;
     {
-        // per-survivor attempt counts -> 4-attempt units, scanned
-        const int chunk = (nS + BS - 1) / BS;
-        const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
-        i64 units = 0, nex = 0, nin = 0, nsp = 0;
-        int bad = 0;
-        u32 *info = (u32 *)L.hi;  // [2 i] = unit offset, [2 i + 1] = count | exact << 31
-        for (int i = i0; i < i1; i++) {
-            T a = AddrOf<W>::make(L.k0[i], W == 2 ? L.k1[i] : 0);
-            double c = bitsd(L.lo[i]);
-            u32 cnt;
-            bool ex;
-            spawn_info<W, MODEL>(I, a, c, myrow, cnt, ex, bad);
-            info[2 * i + 1] = cnt | (ex ? 0x80000000u : 0u);
-            units += (cnt + 3) / 4;
-            nsp += cnt;
-            if (ex) nex++; else nin++;
-        }
-        if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
-        mark(5);
-        i64 utot;
+        i64 units = 0;
+        for (int i = i0; i < i1; i++) units += ((info[2 * i + 1] & 0x7fffffffu) + 3) / 4;
         i64 ubase = block_excl_scan<BS>(units, L.misc, utot);
         for (int i = i0; i < i1; i++) {
             info[2 * i] = (u32)ubase;
             ubase += ((info[2 * i + 1] & 0x7fffffffu) + 3) / 4;
         }
-        // spawn statistics belong to row spawn_step (parents of c^(spawn_step - 1))
-        {
-            i64 t_ex, t_in, t_sp;
-            block_excl_scan<BS>(nex, L.misc, t_ex);
-            block_excl_scan<BS>(nin, L.misc, t_in);
-            block_excl_scan<BS>(nsp, L.misc, t_sp);
-            if (tid == 0) {
-                SpawnPart sp;
-                sp.exact = t_ex;
-                sp.inexact = t_in;
-                sp.spawns = t_sp;
-                sp.pad = 0;
-                I.spart[spawn_step & 1][b] = sp;
-            }
-        }
-
-        mark(6);
-        char *ob = I.slab[out_par];
-        int *on = I.slab_n[out_par];
-        const double dtau = I.dtau;
-        for (i64 j = tid; j < utot; j += BS) {
-            // parent: largest i with offset[i] <= j
-            int lo_i = 0, hi_i = nS - 1;
-            while (lo_i < hi_i) {
-                int mid = (lo_i + hi_i + 1) >> 1;
-                if ((i64)info[2 * mid] <= j) lo_i = mid; else hi_i = mid - 1;
-            }
-            const int i = lo_i;
-            const u32 inf = info[2 * i + 1];
-            const u32 cnt = inf & 0x7fffffffu;
-            const bool ex = inf >> 31;
-            const u32 qu = (u32)(j - (i64)info[2 * i]);
-            const u64 a0 = L.k0[i], a1 = W == 2 ? L.k1[i] : 0;
-            const T a = AddrOf<W>::make(a0, a1);
-            const double c = bitsd(L.lo[i]);
-            const u32 k0 = 4 * qu, k1 = min(cnt, k0 + 4);
-            // scatter one spawn record to its destination bucket
-            auto emit = [&](const T &dd, double vv, u32 k) {
-                const u64 hh = addr_hash(dd);
-                const u32 db = bucket_of(hh, I.log2B);
-                const int pos = atomicAdd(&on[db], 1);
-                if (pos < I.cap_s) store_rec<W>(ob, (i64)db * I.cap_s + pos, dd, vv);
-                else set_error(ctrl, FQE_CAP_SLAB, (int)db);
-                if (I.flags & 1) {
-                    i64 di = atomicAdd((unsigned long long *)&ctrl->dump_spawn_n, 1ull);
-                    if (di < I.dump_cap) {
-                        I.dsp_parent[di * W] = a0;
-                        if (W == 2) I.dsp_parent[di * W + 1] = a1;
-                        I.dsp_attempt[di] = (i64)k;
-                        I.dsp_dest[di * W] = word0(dd);
-                        if (W == 2) I.dsp_dest[di * W + 1] = word1(dd);
-                        I.dsp_val[di] = vv;
-                    }
-                }
-            };
-            if (MODEL == 0) {
-                const T st = run_starts(a);
-                const int o = popc(st);
-                const u32 m = 2 * o;
-                R4 r = {0, 0, 0, 0};
-                double qd = 0.0;
-                if (!ex) {
-                    r = draw(I.seed, a0, a1, spawn_step, 0u, qu);
-                    qd = (double)m / (double)cnt;
-                }
-                for (u32 k = k0; k < k1; k++) {
-                    int idx = ex ? (int)k : (int)pick(rword(r, (int)(k - k0)), m);
-                    double h;
-                    T dd = real_entry(I.mc, a, st, o, idx, h);
-                    double vv = (-(dtau * h)) * c;
-                    if (!ex) vv = vv * qd;
-                    emit(dd, vv, k);
-                }
-            } else {
-                MomRow R = mom_row(myrow);
-                mom_decode(I.mc, a, R);
-                const int P = mom_npairs(R);
-                R4 r = {0, 0, 0, 0};
-                for (u32 k = k0; k < k1; k++) {
-                    int pp, qq, di;
-                    double h;
-                    if (ex) {
-                        mom_entry(R, I.mc.M, (i64)k, pp, qq, di);
-                        T dd = mom_move(I.mc, a, R, pp, qq, di, h);
-                        emit(dd, (-(dtau * h)) * c, k);
-                    } else {
-                        if ((k & 1u) == 0u || k == k0) r = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
-                        u32 w0 = rword(r, 2 * (int)(k & 1u)), w1 = rword(r, 2 * (int)(k & 1u) + 1);
-                        mom_pair(R, (int)pick(w0, (u32)P), pp, qq);
-                        const int Rk = mom_R((pp + qq) % I.mc.M, I.mc.M);
-                        di = (int)pick(w1, (u32)Rk);
-                        T dd = mom_move(I.mc, a, R, pp, qq, di, h);
-                        const double qn = (double)((i64)P * Rk) / (double)cnt;
-                        emit(dd, ((-(dtau * h)) * c) * qn, k);
-                    }
-                }
-            }
-        }
     }
-    if (timing) { __syncthreads(); mark(7); }
+    __syncthreads();
+    mark(6);
+    const i64 u_split = tot_e == 0 ? 0 : (tot_e < nS ? (i64)info[2 * tot_e] : utot);
+    spawn_units<W, MODEL, BS, true>(I, L, b, par, spawn_step, nS, info, perm, par, 0, u_split);
+    spawn_units<W, MODEL, BS, false>(I, L, b, par, spawn_step, nS, info, perm, par, u_split, utot);
+    mark(7);
+}
+
+// ---------------------------------------------------------------- partition
+
+// Second pass of the spawn partition: workgroup cs reads coarse sub-slab cs
+// (group g = cs >> log2SUB) and splits it into the B/G buckets of the group in
+// rounds of RPT records per thread (LDS ranks, one reservation per bucket and
+// round, stores into the reserved runs).  Releases the coarse sub-slab.
+template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I, const int cs)
+{
+    typedef typename AddrOf<W>::T T;
+    __shared__ int s_err;
+    __shared__ int cnt[256];
+    __shared__ i64 base[256];
+    Ctrl *ctrl = I.ctrl;
+    const int tid = threadIdx.x;
+    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_err) return;
+    const int q = ctrl->spawn_par;
+    const int g = cs >> I.log2SUB;
+    const int log2F = I.log2B - I.log2G;
+    const int F = 1 << log2F;
+    const int n = min(I.coarse_n[cs], (int)I.cap_c);
+    const char *src = I.coarse + (i64)cs * I.cap_c * (i64)sizeof(Rec<W>);
+    for (int r0 = 0; r0 < n; r0 += BS * RPT) {
+        if (tid < F) cnt[tid] = 0;
+        __syncthreads();
+        u64 a0[RPT], a1[RPT];
+        double v[RPT];
+        int lb[RPT], rk[RPT];
+#pragma unroll
+        for (int e = 0; e < RPT; e++) {
+            const int i = r0 + e * BS + tid;
+            lb[e] = -1;
+            if (i < n) {
+                load_rec<W>(src, i, a0[e], a1[e], v[e]);
+                lb[e] = (int)(bucket_of(addr_hash(AddrOf<W>::make(a0[e], a1[e])), I.log2B) & (u32)(F - 1));
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < RPT; e++)
+            if (lb[e] >= 0) rk[e] = atomicAdd(&cnt[lb[e]], 1);
+        __syncthreads();
+        if (tid < F) {
+            const int c = cnt[tid];
+            base[tid] = c ? (i64)atomicAdd(&I.slab_n[q][(g << log2F) + tid], c) : 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < RPT; e++) {
+            if (lb[e] < 0) continue;
+            const i64 pos = base[lb[e]] + rk[e];
+            const i64 d = ((i64)g << log2F) + lb[e];
+            if (pos < I.cap_s) store_rec<W>(I.slab[q], d * I.cap_s + pos, AddrOf<W>::make(a0[e], a1[e]), v[e]);
+            else set_error(ctrl, FQE_CAP_SLAB, (int)d);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) I.coarse_n[cs] = 0;
 }
 
 // ---------------------------------------------------------------- finalize

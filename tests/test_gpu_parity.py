@@ -108,6 +108,10 @@ CASES = [
     (1, 7, 6, 2.0, 1e-3, 400, 8, 2, 4, 2048, 256, 2.0),
     (0, 7, 7, 1.0, 1e-3, 300, 9, 1, 2, 2048, 512, float("inf")),
     (0, 7, 7, 1.0, 1e-3, 300, 10, 1, 2, 2048, 512, 0.0),
+    # two-pass spawn partition (B > 64)
+    (0, 12, 12, 6.0, 1e-3, 3000, 15, 1, 256, 2048, 512, 1.0),
+    (0, 20, 20, 6.0, 1e-3, 3000, 16, 2, 128, 2048, 1024, 1.0),
+    (1, 10, 10, 4.0, 1e-3, 2500, 17, 1, 128, 2048, 1024, 1.0),
 ]
 
 
