@@ -8,11 +8,13 @@ timed), then exactly `--steps` steps are timed between two
 torch.cuda.synchronize() calls.
 
 value = walker-steps/s = sum over the timed steps of ||c^(n)||_1 / wall time.
-The roofline object prices the fused step kernel (one launch per step) by
-its algorithmic HBM bytes, 16 B x (table read + spawn records read + table
-written + spawn records written), over its mean launch time measured with
-HIP events on the stream it runs on.  The CPU oracle is timed on a bounded
-sample of the same steady-state vector.
+A step is four launches: merge, spawn, spawn partition, shift update.  The
+roofline object prices the slower of the merge and spawn kernels by its
+algorithmic HBM bytes (merge of step k: read c^(k-1) and the spawn records of
+step k, write c^(k); spawn: read c^(k), write the spawn records of step k+1;
+16 bytes per entry or record for one address word) over its mean launch time
+measured with HIP events on the stream it runs on.  The CPU oracle is timed
+on a bounded sample of the same steady-state vector.
 
 Prints one JSON line.
 """
@@ -101,6 +103,9 @@ def main():
     ap.add_argument("--buckets", type=int, default=None)
     ap.add_argument("--slots", type=int, default=None)
     ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a streaming negation over this many MiB (reads and writes "
+                         "that many bytes): the reference kernel for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
@@ -119,6 +124,15 @@ def main():
     steps = wl["steps"] if args.steps is None else args.steps
     warmup = wl["warmup"] if args.warmup is None else args.warmup
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * 2**20 // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        torch.cuda.empty_cache()
     s = make_solver(fq, wl, cfg, **({"flags": fq.FLAG_PHASE_TIMING} if args.diag else {}))
     occ = synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"])
     a = fq.encode(occ, cfg["W"])
