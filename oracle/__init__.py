@@ -102,6 +102,8 @@ def lib():
         L.orc_lanczos.argtypes = [P(Ham), u64p, C.c_int, f64p, f64p, i32p]
         L.orc_validate.restype = C.c_int
         L.orc_validate.argtypes = [P(Ham)]
+        L.orc_sampled_pair.restype = C.c_int
+        L.orc_sampled_pair.argtypes = [P(Ham), u64p, C.c_int, i32p, i32p]
         _lib = L
     return _lib
 
@@ -223,6 +225,15 @@ def column(h, words, cap=1 << 16):
     m = _check(lib().orc_column(C.byref(h), _p(a, C.c_uint64), _p(dest, C.c_uint64),
                                 _p(vals, C.c_double), cap, C.byref(diag)), "column")
     return diag.value, dest[:m].copy(), vals[:m].copy()
+
+
+def sampled_pair(h, words, pi):
+    """Modes (p, q) of the removal pair with sampling index pi (momentum space)."""
+    a = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    p, q = C.c_int32(0), C.c_int32(0)
+    _check(lib().orc_sampled_pair(C.byref(h), _p(a, C.c_uint64), int(pi), C.byref(p), C.byref(q)),
+           "sampled_pair")
+    return p.value, q.value
 
 
 def validate(h):

@@ -263,11 +263,12 @@ typedef struct {
     /* momentum space: pair structure used by the two-stage sampler */
     int npairs;
     int *pair_off;       /* first column entry of each pair, npairs+1 */
+    int (*pair_pq)[2];   /* modes (p, q), p <= q, of each pair in column order */
 } orc_col;
 
 static void col_free(orc_col *c)
 {
-    free(c->dest); free(c->h); free(c->pair_off);
+    free(c->dest); free(c->h); free(c->pair_off); free(c->pair_pq);
     memset(c, 0, sizeof *c);
 }
 
@@ -368,11 +369,16 @@ static int mom_column(const orc_ham *H, const int32_t *occ, orc_col *c)
     int32_t tmp[ORC_MAXM];
     int npairs = 0;
     int *off = malloc(sizeof(int) * (size_t)(o * (o + 1) / 2 + 2));
-    if (!off) return ORC_ENOMEM;
+    int (*pq)[2] = malloc(sizeof(int[2]) * (size_t)(o * (o + 1) / 2 + 2));
+    if (!off || !pq) { free(off); free(pq); return ORC_ENOMEM; }
+    c->pair_off = off;
+    c->pair_pq = pq;
     for (int a = 0; a < o; a++) {
         for (int b = a; b < o; b++) {
             int p = list[a], q = list[b];
             if (p == q && occ[p] < 2) continue;
+            pq[npairs][0] = p;
+            pq[npairs][1] = q;
             off[npairs++] = c->n;
             int K = (p + q) % M;
             int cnt = mom_pair_count(K, M);
@@ -388,13 +394,12 @@ static int mom_column(const orc_ham *H, const int32_t *occ, orc_col *c)
                 memcpy(tmp, occ, sizeof(int32_t) * (size_t)M);
                 tmp[p] -= 1; tmp[q] -= 1; tmp[r] += 1; tmp[s] += 1;
                 int rc = col_push(c, tmp, M, h);
-                if (rc) { free(off); return rc; }
+                if (rc) return rc;
             }
         }
     }
     off[npairs] = c->n;
     c->npairs = npairs;
-    c->pair_off = off;
     return ORC_OK;
 }
 
@@ -446,11 +451,58 @@ int orc_column(const orc_ham *H, const uint64_t *a, uint64_t *dest, double *h, i
  * destination uniform over that pair's R(K) destinations; generation
  * probability 1/(P R).  Returns the column entry and sets *qnum = m or P R,
  * the inverse generation probability. */
-static int column_pick(const orc_ham *H, const orc_col *c, uint32_t r0, uint32_t r1, int64_t *qnum)
+/* The uniform pair index of the sampler (Sec. 6.3) names a pair in the
+ * sampling order, which need not be the column order: any fixed one-to-one
+ * order gives every pair probability 1/P.  Sampling order: first the pairs
+ * (p, p) of the modes with n_p >= 2, p ascending; then the pairs of two
+ * distinct occupied modes, the i-th and j-th occupied mode (i < j, counted
+ * from 0 in ascending mode order) at index j(j-1)/2 + i.  Returns the
+ * position of the pair in the column order. */
+static int sampled_pair(const orc_col *c, const int32_t *occ, int M, int pi)
+{
+    int list[ORC_MAXM], o = 0, p = -1, q = -1;
+    for (int j = 0; j < M; j++) if (occ[j] > 0) list[o++] = j;
+    for (int j = 0; j < M && p < 0; j++) {
+        if (occ[j] >= 2) {
+            if (pi == 0) p = q = j;
+            pi--;
+        }
+    }
+    for (int jj = 1; jj < o && p < 0; jj++) {
+        for (int ii = 0; ii < jj && p < 0; ii++) {
+            if (pi == 0) { p = list[ii]; q = list[jj]; }
+            pi--;
+        }
+    }
+    for (int k = 0; k < c->npairs; k++)
+        if (c->pair_pq[k][0] == p && c->pair_pq[k][1] == q) return k;
+    return -1; /* not reached for 0 <= pi < P */
+}
+
+/* Exported for tests: modes (p, q) of the pair with sampling index pi of the
+ * momentum-space parent a. */
+int orc_sampled_pair(const orc_ham *H, const uint64_t *a, int pi, int *p, int *q)
+{
+    if (orc_validate(H) || H->model != ORC_MOM1D) return ORC_EINVAL;
+    int32_t occ[ORC_MAXM];
+    orc_decode(a, H->M, H->N, occ);
+    orc_col c;
+    int rc = ham_column(H, occ, &c);
+    if (rc) { col_free(&c); return rc; }
+    if (pi < 0 || pi >= c.npairs) { col_free(&c); return ORC_EINVAL; }
+    int k = sampled_pair(&c, occ, H->M, pi);
+    *p = c.pair_pq[k][0];
+    *q = c.pair_pq[k][1];
+    col_free(&c);
+    return ORC_OK;
+}
+
+static int column_pick(const orc_ham *H, const orc_col *c, const int32_t *occ, uint32_t r0, uint32_t r1,
+                       int64_t *qnum)
 {
     if (H->model == ORC_MOM1D) {
         int P = c->npairs;
-        int pi = (int)pick(r0, (uint32_t)P);
+        int pi = sampled_pair(c, occ, H->M, (int)pick(r0, (uint32_t)P));
         int R = c->pair_off[pi + 1] - c->pair_off[pi];
         int di = (int)pick(r1, (uint32_t)R);
         *qnum = (int64_t)P * R;
@@ -629,7 +681,7 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
                     r0 = r[k & 3];
                 }
                 int64_t qnum;
-                int e = column_pick(H, &c, r0, r1, &qnum);
+                int e = column_pick(H, &c, occ, r0, r1, &qnum);
                 double q = (double)qnum / (double)ni;
                 double v = ((-(P->dtau * c.h[e])) * ci) * q;
                 rec[nr].a[0] = c.dest[e][0]; rec[nr].a[1] = c.dest[e][1]; rec[nr].v = v; nr++;

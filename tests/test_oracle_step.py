@@ -196,3 +196,25 @@ def test_c1_oracle_energies_within_3_sigma_of_ed(orc):
     # bookkeeping invariants of the time series (Sec. 4, row semantics)
     assert np.all(st["exact_steps"][1:] + st["inexact_steps"][1:] == st["len"][:-1])
     assert st["step"][0] == 1 and st["step"][-1] == 10000
+
+
+@pytest.mark.parametrize("M,N", [(5, 4), (8, 8), (16, 16), (7, 12)])
+def test_sampled_pair_order_is_a_bijection(orc, M, N):
+    """The stochastic removal-pair choice (Sec. 6.3) maps the P sampling
+    indices one to one onto the valid pairs {p <= q occupied, n_p >= 2 when
+    p = q}, so the uniform index gives each pair probability 1/P.  Checked
+    for random parents against the pair set built from the occupations."""
+    rng = np.random.default_rng(5)
+    h = orc.ham(orc.MOM1D, M, N, 1.0, 2.0)
+    for _ in range(25):
+        occ = np.zeros(M, int)
+        for x in rng.integers(0, M, N):
+            occ[x] += 1
+        a = orc.encode(list(occ))
+        want = {(p, q) for p in range(M) for q in range(p, M)
+                if occ[p] > 0 and occ[q] > 0 and (p != q or occ[p] >= 2)}
+        got = [orc.sampled_pair(h, a, i) for i in range(len(want))]
+        assert len(set(got)) == len(got) == len(want)
+        assert set(got) == want
+        with pytest.raises(Exception):
+            orc.sampled_pair(h, a, len(want))
