@@ -36,14 +36,14 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "c3": dict(cfg="c3", name="mom1d_M16_N16_u4_dtau5e-4_Nt1e8",
-               table_capacity=19_500_000, spawn_capacity=200_000_000, buckets=8192,
-               lds_slots=4096, block=1024, warmup=3000, steps=1000),
+               table_capacity=19_500_000, spawn_capacity=200_000_000, buckets=16384,
+               lds_slots=2048, block=512, spawn_block=256, warmup=3000, steps=1000),
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
                table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=0,
-               lds_slots=4096, block=1024, warmup=6000, steps=1000),
+               lds_slots=4096, block=1024, spawn_block=256, warmup=6000, steps=1000),
     "c1": dict(cfg="c1", name="real1d_M6_N6_u6_dtau1e-3_Nt1e3",
                table_capacity=1024, spawn_capacity=8192, buckets=0, lds_slots=0, block=0,
-               warmup=0, steps=10_000),
+               spawn_block=0, warmup=0, steps=10_000),
 }
 
 
@@ -55,7 +55,8 @@ def make_solver(fq, wl, cfg, **over):
     kw = dict(t=cfg["t"], u=cfg["u"], dtau=cfg["dtau"], target_walkers=cfg["target"],
               seed=cfg["seed"], addr_words=cfg["W"], threshold=cfg["theta"],
               table_capacity=wl["table_capacity"], spawn_capacity=wl["spawn_capacity"],
-              buckets=wl["buckets"], lds_slots=wl["lds_slots"], block=wl["block"])
+              buckets=wl["buckets"], lds_slots=wl["lds_slots"], block=wl["block"],
+              spawn_block=wl["spawn_block"])
     kw.update(over)
     return fq.Solver(cfg["model"], cfg["M"], cfg["N"], **kw)
 
@@ -103,6 +104,7 @@ def main():
     ap.add_argument("--buckets", type=int, default=None)
     ap.add_argument("--slots", type=int, default=None)
     ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--spawn-block", type=int, default=None)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a streaming negation over this many MiB (reads and writes "
                          "that many bytes): the reference kernel for HBM byte counters")
@@ -117,7 +119,8 @@ def main():
     import paper_2601_19505_amd as fq
 
     wl = dict(WORKLOADS[args.workload])
-    for k_arg, k_wl in (("buckets", "buckets"), ("slots", "lds_slots"), ("block", "block")):
+    for k_arg, k_wl in (("buckets", "buckets"), ("slots", "lds_slots"), ("block", "block"),
+                        ("spawn_block", "spawn_block")):
         if getattr(args, k_arg) is not None:
             wl[k_wl] = getattr(args, k_arg)
     cfg = synthetic.CONFIGS[wl["cfg"]]
@@ -138,7 +141,7 @@ def main():
     a = fq.encode(occ, cfg["W"])
     s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
     log(f"[bench] workload {wl['name']}: layout buckets={s.layout.buckets} "
-        f"slots={s.layout.lds_slots} block={s.layout.block} workspace={s.nbytes / 2**30:.2f} GiB")
+        f"slots={s.layout.lds_slots} block={s.layout.block} spawn_block={s.layout.spawn_block} workspace={s.nbytes / 2**30:.2f} GiB")
     t0 = time.perf_counter()
     done = 0
     warm = []
@@ -208,6 +211,7 @@ def main():
                    "target_walkers": cfg["target"], "seed": cfg["seed"],
                    "addr_words": cfg["W"], "buckets": s.layout.buckets,
                    "lds_slots": s.layout.lds_slots, "block": s.layout.block,
+                   "spawn_block": s.layout.spawn_block,
                    "mean_norm": float(st["norm"].mean()), "mean_len": float(st["len"].mean()),
                    "mean_spawns": float(st["spawns"].mean())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -109,11 +109,13 @@ typedef struct {
 /* Sizes of the device data structures.  table_capacity: largest number of
  * stored addresses; spawn_capacity: largest number of spawn events per step;
  * buckets: hash buckets (power of two, 0 = choose); lds_slots: LDS hash slots
- * per bucket (power of two, 1024..8192, 0 = 4096); block: threads per
- * workgroup (256, 512 or 1024; 0 = choose). */
+ * per bucket (power of two, 1024..8192, <= 8 * block, 0 = 4096); block:
+ * threads per workgroup of the merge kernel (256, 512 or 1024; 0 = choose);
+ * spawn_block: threads per workgroup of the spawn kernel (256, 512 or 1024;
+ * 0 = 256). */
 typedef struct {
     int64_t table_capacity, spawn_capacity;
-    int32_t buckets, lds_slots, block, reserved;
+    int32_t buckets, lds_slots, block, spawn_block;
 } fq_layout;
 
 typedef struct fq_handle fq_handle;

@@ -46,7 +46,7 @@ class Params(C.Structure):
 class Layout(C.Structure):
     _fields_ = [("table_capacity", C.c_int64), ("spawn_capacity", C.c_int64),
                 ("buckets", C.c_int32), ("lds_slots", C.c_int32), ("block", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("spawn_block", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -146,7 +146,8 @@ class Solver:
 
     def __init__(self, model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08,
                  xi=None, threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0,
-                 table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0):
+                 table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0,
+                 spawn_block=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the FCIQMC solver needs a GPU")
@@ -158,7 +159,7 @@ class Solver:
         self.W = addr_words
         nbytes, lay = workspace_size(self.ham, self.params,
                                      Layout(table_capacity, spawn_capacity, buckets, lds_slots,
-                                            block, 0))
+                                            block, spawn_block))
         self.layout = lay
         self.nbytes = nbytes
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")

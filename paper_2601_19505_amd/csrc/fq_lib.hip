@@ -41,9 +41,16 @@ __global__ __launch_bounds__(BS) void k_spawn(const Inst *I, int mode)
 
 __global__ __launch_bounds__(1024) void k_finalize(const Inst *I) { finalize_instance<1024>(*I); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (blockIdx mod 8).
+// All sub-slabs of one group go to the same XCD, so the runs that different
+// workgroups append to one bucket's slab meet in that XCD's L2 and partial
+// cache lines are merged before they are written back.
 template <int W> __global__ __launch_bounds__(1024) void k_part(const Inst *I)
 {
-    partition_coarse<W, 1024, 8>(*I, (int)blockIdx.x);
+    const int x = (int)blockIdx.x, xcd = x & 7, j = x >> 3;
+    const int g = ((j >> I->log2SUB) << 3) | xcd;
+    const int sub = j & ((1 << I->log2SUB) - 1);
+    partition_coarse<W, 1024, 8>(*I, (g << I->log2SUB) | sub);
 }
 
 // insert host-staged entries into table[parity] and accumulate the norm
@@ -212,7 +219,7 @@ size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8; }
 constexpr size_t LDS_MAX = 160 * 1024;
 
 struct Resolved {
-    int W, nb, B, log2B, slots, block, two_pass, log2G, log2SUB;
+    int W, nb, B, log2B, slots, block, spawn_block, two_pass, log2G, log2SUB;
     i64 cap_t, cap_s, cap_c, dump_cap;
     size_t off_ctrl, off_inst, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
@@ -260,6 +267,11 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     if (L.block == 0) L.block = h->model == FQ_MOM1D ? 512 : 1024;
     if (L.block != 256 && L.block != 512 && L.block != 1024) { err = "block must be 256, 512 or 1024"; return FQ_EINVAL; }
     if (L.lds_slots > 8 * L.block) { err = "lds_slots must be <= 8 * block"; return FQ_EINVAL; }
+    if (L.spawn_block == 0) L.spawn_block = 256;
+    if (L.spawn_block != 256 && L.spawn_block != 512 && L.spawn_block != 1024) {
+        err = "spawn_block must be 256, 512 or 1024";
+        return FQ_EINVAL;
+    }
     if (lds_bytes(R.W, L.lds_slots) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
     if (L.buckets == 0) {
         double uniq = (double)L.table_capacity + 0.25 * (double)L.spawn_capacity;
@@ -275,6 +287,7 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     R.log2B = ilog2(R.B);
     R.slots = L.lds_slots;
     R.block = L.block;
+    R.spawn_block = L.spawn_block;
     auto cap = [](double mean) {
         double c = mean + 8.0 * std::sqrt(mean) + 64.0;
         return (i64)std::ceil(c);
@@ -508,7 +521,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
     const void *km = step_kernel(R.W, variant(h->model, h->M), R.block, false);
-    const void *ks = step_kernel(R.W, variant(h->model, h->M), R.block, true);
+    const void *ks = step_kernel(R.W, variant(h->model, h->M), R.spawn_block, true);
     hipError_t e = hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
@@ -579,9 +592,9 @@ static int launch_merge(fq_handle *q, hipStream_t s)
 static int launch_spawn(fq_handle *q, int mode, hipStream_t s)
 {
     const Resolved &R = q->R;
-    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.block, true);
+    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.spawn_block, true);
     void *args[] = {(void *)&q->d_inst, (void *)&mode};
-    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lds_spawn_bytes(R.cap_t), s));
+    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.spawn_block), args, lds_spawn_bytes(R.cap_t), s));
     return FQ_OK;
 }
 

@@ -207,6 +207,67 @@ __device__ __forceinline__ T mom_move(const ModelConst &C, const MomP<T> &P, int
     return d;
 }
 
+// One stochastic spawn of a momentum-space parent (Sec. 6.3, two-stage
+// sampler): w0 picks the removal pair uniformly over the P pairs through the
+// sampling order (first the pairs (p, p) of doubly occupied modes, p
+// ascending; then the pairs of the i-th and j-th occupied mode, i < j, at
+// index j(j-1)/2 + i), w1 picks one of the pair's R(K) destinations in column
+// order.  Returns the destination, its matrix element h and qnum = P R, the
+// inverse generation probability.  No data-dependent branches, so the lanes
+// of a wave stay converged.
+template <class T>
+__device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u32 w1, double &h, i64 &qnum)
+{
+    const int M = C.M;
+    const T st = run_starts(a);
+    const T z = ~a & mask_below<T>(C.nb);
+    const int o = popc(st);
+    const T dpos = st & shr(a, 1);  // run starts of modes with n >= 2
+    const int D = popc(dpos);
+    const int P = o * (o - 1) / 2 + D;
+    const int pi = (int)pick(w0, (u32)P);
+    const bool diag = pi < D;
+    const int t = diag ? 0 : pi - D;
+    // j = largest integer with j (j - 1) / 2 <= t; the float root is exact to
+    // within one and corrected
+    int j = (int)((1.0f + __fsqrt_rn(1.0f + 8.0f * (float)t)) * 0.5f);
+    j -= (j * (j - 1) / 2 > t) ? 1 : 0;
+    j += ((j + 1) * j / 2 <= t) ? 1 : 0;
+    const int i = t - j * (j - 1) / 2;
+    const T x = diag ? dpos : st;
+    const int sp = select(x, diag ? pi : i);
+    const int sq = select(x, diag ? pi : j);
+    const int p = sp - popc(a & mask_below<T>(sp));
+    const int q = sq - popc(a & mask_below<T>(sq));
+    const int K = mod_add(p, q, M);
+    const int R = mom_R(K, M);
+    const int di = (int)pick(w1, (u32)R);
+    const int half = K / 2;
+    const int idxp = p <= half ? p : half + 1 + (p - K - 1);
+    const int idx = di < idxp ? di : di + 1;
+    const int r = idx <= half ? idx : K + 1 + (idx - half - 1);
+    int s = K - r;
+    if (s < 0) s += M;
+    const int sr = r == 0 ? 0 : select(z, r - 1) + 1;
+    const int ss = s == 0 ? 0 : select(z, s - 1) + 1;
+    const int np = runlen(a, sp), nq = runlen(a, sq), nr = runlen(a, sr), ns = runlen(a, ss);
+    const int A = np * (nq - (p == q ? 1 : 0));
+    const int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
+    const int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);
+    h = (C.coef * (double)cc) * (C.sq[A] * C.sq[B]);
+    qnum = (i64)P * R;
+    // remove one boson at the start of runs q and p (higher first), then add
+    // one at the start of runs r and s, whose starts moved down by one for
+    // each removal from a lower mode (higher insertion first)
+    T d = del_bit(a, sq);
+    d = del_bit(d, sp);
+    const int r2 = sr - (p < r ? 1 : 0) - (q < r ? 1 : 0);
+    const int s2 = ss - (p < s ? 1 : 0) - (q < s ? 1 : 0);
+    d = ins_one(d, max(r2, s2));
+    d = ins_one(d, min(r2, s2));
+    return d;
+}
+
 // pair index -> (p, q) in the canonical pair order: occupied p ascending,
 // then (p, p) when n_p >= 2, then (p, q) for occupied q > p
 template <class T>
@@ -324,53 +385,76 @@ template <class T> __device__ __forceinline__ void mom_it_next(const MomP<T> &P,
 }
 
 // A momentum-space parent with the start bit of every mode packed into
-// registers (byte j of pos = first bit of the run of mode j, byte M = N+M), so
-// a destination's occupation and position cost a few instructions.  MAXM is
-// the compile-time bound on M.
+// registers: byte j&3 of word j>>2 is the first bit of the run of mode j, and
+// `end` = N+M is where a virtual mode M would start, so a destination's
+// occupation and position cost a few instructions.  MAXM (16 or 32) is the
+// compile-time bound on M.  The words are separate members, not an array, so
+// that no dynamically indexed private memory is created.
 template <class T, int MAXM> struct MomD {
-    static constexpr int NW = MAXM / 8 + 1;
     MomP<T> P;
-    u64 pos[NW];
+    u32 w0, w1, w2, w3, w4, w5, w6, w7;
+    int end;
 };
 
-template <int NW> __device__ __forceinline__ int byte_at(const u64 *w, int j)
+template <class T, int MAXM> __device__ __forceinline__ void mom_set_byte(MomD<T, MAXM> &D, int j, u32 v)
 {
-    u64 x = w[0];
-#pragma unroll
-    for (int k = 1; k < NW; k++) x = j >= 8 * k ? w[k] : x;
-    return (int)((x >> ((j & 7) * 8)) & 0xffull);
+    const u32 x = v << ((j & 3) * 8);
+    switch (j >> 2) {
+    case 0: D.w0 |= x; break;
+    case 1: D.w1 |= x; break;
+    case 2: D.w2 |= x; break;
+    case 3: D.w3 |= x; break;
+    case 4: D.w4 |= x; break;
+    case 5: D.w5 |= x; break;
+    case 6: D.w6 |= x; break;
+    default: D.w7 |= x; break;
+    }
 }
 
 template <class T, int MAXM> __device__ __forceinline__ MomD<T, MAXM> mom_decode_packed(const ModelConst &C, T a)
 {
+    static_assert(MAXM == 16 || MAXM == 32, "MAXM");
     MomD<T, MAXM> D;
     D.P.a = a;
     D.P.st = run_starts(a);
     D.P.z = ~a & mask_below<T>(C.nb);
     D.P.o = popc(D.P.st);
     D.P.dbl = popc(D.P.st & shr(a, 1));
-#pragma unroll
-    for (int w = 0; w < MomD<T, MAXM>::NW; w++) D.pos[w] = 0;
-    T zz = D.P.z | one_at<T>(C.nb);  // separators plus a virtual one after the last mode
+    D.w0 = D.w1 = D.w2 = D.w3 = D.w4 = D.w5 = D.w6 = D.w7 = 0u;
+    D.end = C.nb + 1;
+    T zz = D.P.z;  // separators: mode j starts one bit after the j-th zero
     int prev = 0, oo = 0;
 #pragma unroll
-    for (int j = 1; j <= MAXM; j++) {
-        if (j <= C.M) {
+    for (int j = 1; j < MAXM; j++) {
+        if (j < C.M) {
             const int z0 = ctz(zz);
             zz = zz & ~one_at<T>(z0);
             const int sj = z0 + 1;
             oo += ((j - 1) & 1) & (sj - prev - 1 > 0 ? 1 : 0);
-            D.pos[j >> 3] |= (u64)sj << ((j & 7) * 8);
+            mom_set_byte(D, j, (u32)sj);
             prev = sj;
         }
     }
+    // the last mode M-1 ends at the virtual start N+M
+    oo += ((C.M - 1) & 1) & (D.end - prev - 1 > 0 ? 1 : 0);
     D.P.o_odd = oo;
     return D;
 }
 
-template <class T, int MAXM> __device__ __forceinline__ int mom_pos(const MomD<T, MAXM> &D, int j)
+// first bit of mode j (0 <= j <= M; j = M gives N+M)
+template <class T, int MAXM> __device__ __forceinline__ int mom_pos(const ModelConst &C, const MomD<T, MAXM> &D, int j)
 {
-    return byte_at<MomD<T, MAXM>::NW>(D.pos, j);
+    // the word is picked with masks, not selects between members: a select
+    // between two members is turned into one load at a computed address, which
+    // sends the whole struct to private memory
+    const u32 k = (u32)j >> 2;
+    u32 x = (D.w0 & (0u - (u32)(k == 0u))) | (D.w1 & (0u - (u32)(k == 1u))) | (D.w2 & (0u - (u32)(k == 2u))) |
+            (D.w3 & (0u - (u32)(k == 3u)));
+    if (MAXM > 16)
+        x |= (D.w4 & (0u - (u32)(k == 4u))) | (D.w5 & (0u - (u32)(k == 5u))) | (D.w6 & (0u - (u32)(k == 6u))) |
+             (D.w7 & (0u - (u32)(k == 7u)));
+    const int v = (int)((x >> ((j & 3) * 8)) & 0xffu);
+    return j == C.M ? D.end : v;
 }
 
 // move {p,q} -> {r,s} using the packed start positions
@@ -386,9 +470,9 @@ __device__ __forceinline__ T mom_move_d(const ModelConst &C, const MomD<T, MAXM>
     int r = idx <= half ? idx : K + 1 + (idx - half - 1);
     int s = K - r;
     if (s < 0) s += M;
-    const int sr = mom_pos(D, r), ss = mom_pos(D, s);
-    const int np = mom_pos(D, p + 1) - sp - 1, nq = mom_pos(D, q + 1) - sq - 1;
-    const int nr = mom_pos(D, r + 1) - sr - 1, ns = mom_pos(D, s + 1) - ss - 1;
+    const int sr = mom_pos(C, D, r), ss = mom_pos(C, D, s);
+    const int np = mom_pos(C, D, p + 1) - sp - 1, nq = mom_pos(C, D, q + 1) - sq - 1;
+    const int nr = mom_pos(C, D, r + 1) - sr - 1, ns = mom_pos(C, D, s + 1) - ss - 1;
     int A = np * (nq - (p == q ? 1 : 0));
     int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
     int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);

@@ -278,49 +278,104 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
     }
 }
 
-// ---------------------------------------------------------------- spawn walk
+// ---------------------------------------------------------------- spawn records
 
-// Spawn records of the units [u_lo, u_hi) (all exact or all stochastic).
-// Blocked assignment: thread t walks a contiguous range of units in order, so
-// a parent is decoded once and an exact-column iterator carries over between
-// its units.  Records are partitioned in rounds: one unit per thread into
-// registers, a rank inside the destination group from an LDS atomic, one
-// global atomic per group reserving a contiguous run, then the stores.
-template <int W, int MODEL, int BS, bool EXACT>
-__device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const int b, const int out_par,
-                                            const u32 spawn_step, const int nS, const u32 *info, const u32 *perm,
-                                            const int in_par, const i64 u_lo, const i64 u_hi)
+// Partition of spawn records into destination groups, one round at a time:
+// every thread holds up to NR records, takes a rank inside the record's group
+// from an LDS counter, one thread per group reserves a contiguous run with
+// one global atomic, then the records are stored into the runs.  With the
+// two-pass partition a group is a coarse group of buckets and the run lies in
+// the coarse sub-slab of this workgroup (blockIdx mod 64); otherwise a group
+// is a bucket and the run lies in its slab.
+template <int W> struct SpawnOut {
+    typedef typename AddrOf<W>::T T;
+    const Inst &I;
+    const Lds &L;
+    int out_par, G, gshift, sub;
+    __device__ SpawnOut(const Inst &I_, const Lds &L_, int out_par_) : I(I_), L(L_), out_par(out_par_)
+    {
+        const int log2G = I.two_pass ? I.log2G : I.log2B;
+        G = 1 << log2G;
+        gshift = I.log2B - log2G;
+        sub = (int)(blockIdx.x & ((1u << I.log2SUB) - 1));
+    }
+    __device__ int *gcnt() const { return (int *)(L.misc + 64); }  // G <= 64 counters
+    __device__ i64 *gbase() const { return L.misc + 96; }          // G <= 64 run bases
+    __device__ void begin() const
+    {
+        if ((int)threadIdx.x < G) gcnt()[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    __device__ int group(const T &d) const { return (int)(bucket_of(addr_hash(d), I.log2B) >> gshift); }
+    __device__ int rank(int g) const { return atomicAdd(&gcnt()[g], 1); }
+    __device__ void reserve() const
+    {
+        __syncthreads();
+        const int tid = threadIdx.x;
+        if (tid < G) {
+            const int cg = gcnt()[tid];
+            int *cn = I.two_pass ? &I.coarse_n[(tid << I.log2SUB) + sub] : &I.slab_n[out_par][tid];
+            gbase()[tid] = cg ? (i64)atomicAdd(cn, cg) : 0;
+        }
+        __syncthreads();
+    }
+    __device__ void put(int g, int rk, const T &d, double v, u64 pa0, u64 pa1, u32 k) const
+    {
+        const i64 pos = gbase()[g] + rk;
+        if (I.two_pass) {
+            const i64 cs = ((i64)g << I.log2SUB) + sub;
+            if (pos < I.cap_c) store_rec<W>(I.coarse, cs * I.cap_c + pos, d, v);
+            else set_error(I.ctrl, FQE_CAP_SLAB, g);
+        } else {
+            if (pos < I.cap_s) store_rec<W>(I.slab[out_par], (i64)g * I.cap_s + pos, d, v);
+            else set_error(I.ctrl, FQE_CAP_SLAB, g);
+        }
+        if (I.flags & 1) {
+            i64 di = atomicAdd((unsigned long long *)&I.ctrl->dump_spawn_n, 1ull);
+            if (di < I.dump_cap) {
+                I.dsp_parent[di * W] = pa0;
+                if (W == 2) I.dsp_parent[di * W + 1] = pa1;
+                I.dsp_attempt[di] = (i64)k;
+                I.dsp_dest[di * W] = word0(d);
+                if (W == 2) I.dsp_dest[di * W + 1] = word1(d);
+                I.dsp_val[di] = v;
+            }
+        }
+    }
+};
+
+// Exact columns (Sec. 7.1): the m entries of each exact parent in column
+// order, cut into units of 4 entries; units [0, u_hi) of the nE exact
+// entries (offsets in info[2 i]).  Blocked assignment: thread t walks a
+// contiguous range of units, so a parent is decoded once and the column
+// iterator carries over between its units.
+template <int W, int MODEL, int BS>
+__device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const int b, const int par,
+                                            const u32 spawn_step, const int nE, const u32 *info, const u32 *perm,
+                                            const i64 u_hi)
 {
     typedef typename AddrOf<W>::T T;
     constexpr int MAXM = MODEL == 1 ? 16 : 32;
     const int tid = threadIdx.x;
-    Ctrl *ctrl = I.ctrl;
-    const int log2G = I.two_pass ? I.log2G : I.log2B;
-    const int G = 1 << log2G;
-    const int gshift = I.log2B - log2G;
-    const int sub = (int)(blockIdx.x & ((1u << I.log2SUB) - 1));
-    int *gcnt = (int *)(L.misc + 64);  // G <= 64 counters
-    i64 *gbase = L.misc + 96;          // G <= 64 run bases
+    const SpawnOut<W> out(I, L, par);
     const double dtau = I.dtau;
-    if (b == 0 && tid == 0) ctrl->spawn_par = out_par;
-    const i64 nu = u_hi - u_lo;
+    const i64 nu = u_hi;
     if (nu <= 0) return;
-    const i64 u_beg = u_lo + nu * tid / BS, u_end = u_lo + nu * (tid + 1) / BS;
+    const i64 u_beg = nu * tid / BS, u_end = nu * (tid + 1) / BS;
     const i64 rounds = (nu + BS - 1) / BS;
     i64 u = u_beg;
     int cur = -1;     // current parent
     i64 cur_end = 0;  // first unit of the next parent
     i64 cur_off = 0;
     u32 cnt = 0;
-    double c = 0.0, qd = 0.0;
+    double c = 0.0;
     u64 a0 = 0, a1 = 0;
     T st;
-    int o = 0, np = 0;
+    int o = 0;
     MomD<T, MAXM> D;
     PairIt<T> it;
     for (i64 rr = 0; rr < rounds; rr++) {
-        if (tid < G) gcnt[tid] = 0;
-        __syncthreads();
+        out.begin();
         T d0, d1, d2, d3;
         double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
         int nk = 0;
@@ -330,7 +385,7 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
                 // parent holding unit u: binary search first, then walk forward
                 int i;
                 if (cur < 0) {
-                    int lo_i = 0, hi_i = nS - 1;
+                    int lo_i = 0, hi_i = nE - 1;
                     while (lo_i < hi_i) {
                         int mid = (lo_i + hi_i + 1) >> 1;
                         if ((i64)info[2 * mid] <= u) lo_i = mid; else hi_i = mid - 1;
@@ -338,25 +393,23 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
                     i = lo_i;
                 } else {
                     i = cur + 1;
-                    while (i + 1 < nS && (i64)info[2 * (i + 1)] <= u) i++;
+                    while (i + 1 < nE && (i64)info[2 * (i + 1)] <= u) i++;
                 }
                 cur = i;
                 cur_off = info[2 * i];
-                cur_end = i + 1 < nS ? (i64)info[2 * (i + 1)] : u_hi;
+                cur_end = i + 1 < nE ? (i64)info[2 * (i + 1)] : u_hi;
                 cnt = info[2 * i + 1] & 0x7fffffffu;
                 const i64 e = (i64)b * I.cap_t + perm[i];
-                a0 = I.tab_a[in_par][0][e];
-                a1 = W == 2 ? I.tab_a[in_par][1][e] : 0;
-                c = I.tab_v[in_par][e];
+                a0 = I.tab_a[par][0][e];
+                a1 = W == 2 ? I.tab_a[par][1][e] : 0;
+                c = I.tab_v[par][e];
                 const T a = AddrOf<W>::make(a0, a1);
                 if (MODEL == 0) {
                     st = run_starts(a);
                     o = popc(st);
-                    if (!EXACT) qd = (double)(2 * o) / (double)cnt;
                 } else {
                     D = mom_decode_packed<T, MAXM>(I.mc, a);
-                    np = mom_npairs(D.P);
-                    if (EXACT) mom_it_init(D.P, I.mc.M, (i64)(4 * (u - cur_off)), it);
+                    mom_it_init(D.P, I.mc.M, (i64)(4 * (u - cur_off)), it);
                 }
             }
             const u32 qu = (u32)(u - cur_off);
@@ -364,15 +417,10 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
             nk = (int)min(cnt - k0, 4u);
             if (MODEL == 0) {
                 const T a = AddrOf<W>::make(a0, a1);
-                const u32 m = 2 * o;
-                R4 r = {0, 0, 0, 0};
-                if (!EXACT) r = draw(I.seed, a0, a1, spawn_step, 0u, qu);
                 auto gen = [&](int e, T &dd, double &vv) {
-                    int idx = EXACT ? (int)(k0 + e) : (int)pick(rword(r, e), m);
                     double h;
-                    dd = real_entry(I.mc, a, st, o, idx, h);
+                    dd = real_entry(I.mc, a, st, o, (int)(k0 + e), h);
                     vv = (-(dtau * h)) * c;
-                    if (!EXACT) vv = vv * qd;
                 };
                 gen(0, d0, v0);
                 if (nk > 1) gen(1, d1, v1);
@@ -380,82 +428,93 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
                 if (nk > 3) gen(3, d3, v3);
             } else {
                 const int M = I.mc.M;
-                if (EXACT) {
-                    auto gen = [&](T &dd, double &vv) {
-                        double h;
-                        dd = mom_move_d(I.mc, D, it.pa, it.pb, it.sa, it.sb, it.di, h);
-                        vv = (-(dtau * h)) * c;
-                        mom_it_next(D.P, M, it);
-                    };
-                    gen(d0, v0);
-                    if (nk > 1) gen(d1, v1);
-                    if (nk > 2) gen(d2, v2);
-                    if (nk > 3) gen(d3, v3);
-                } else {
-                    const double cnt_d = (double)cnt;
-                    auto gen = [&](u32 w0, u32 w1, T &dd, double &vv) {
-                        int pp, qq, sp, sq;
-                        mom_pair(D.P, (int)pick(w0, (u32)np), pp, qq, sp, sq);
-                        const int Rk = mom_R(mod_add(pp, qq, M), M);
-                        const int di = (int)pick(w1, (u32)Rk);
-                        double h;
-                        dd = mom_move_d(I.mc, D, pp, qq, sp, sq, di, h);
-                        const double qn = (double)((i64)np * Rk) / cnt_d;
-                        vv = ((-(dtau * h)) * c) * qn;
-                    };
-                    R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k0 >> 1);
-                    gen(r.x, r.y, d0, v0);
-                    if (nk > 1) gen(r.z, r.w, d1, v1);
-                    if (nk > 2) {
-                        r = draw(I.seed, a0, a1, spawn_step, 0u, (k0 >> 1) + 1);
-                        gen(r.x, r.y, d2, v2);
-                        if (nk > 3) gen(r.z, r.w, d3, v3);
-                    }
-                }
+                auto gen = [&](T &dd, double &vv) {
+                    double h;
+                    dd = mom_move_d(I.mc, D, it.pa, it.pb, it.sa, it.sb, it.di, h);
+                    vv = (-(dtau * h)) * c;
+                    mom_it_next(D.P, M, it);
+                };
+                gen(d0, v0);
+                if (nk > 1) gen(d1, v1);
+                if (nk > 2) gen(d2, v2);
+                if (nk > 3) gen(d3, v3);
             }
             u++;
         }
-        // ranks inside the destination groups
         int g0 = 0, g1 = 0, g2 = 0, g3 = 0, rk0 = 0, rk1 = 0, rk2 = 0, rk3 = 0;
-        if (nk > 0) { g0 = (int)(bucket_of(addr_hash(d0), I.log2B) >> gshift); rk0 = atomicAdd(&gcnt[g0], 1); }
-        if (nk > 1) { g1 = (int)(bucket_of(addr_hash(d1), I.log2B) >> gshift); rk1 = atomicAdd(&gcnt[g1], 1); }
-        if (nk > 2) { g2 = (int)(bucket_of(addr_hash(d2), I.log2B) >> gshift); rk2 = atomicAdd(&gcnt[g2], 1); }
-        if (nk > 3) { g3 = (int)(bucket_of(addr_hash(d3), I.log2B) >> gshift); rk3 = atomicAdd(&gcnt[g3], 1); }
-        __syncthreads();
-        // one reservation per group and round
-        if (tid < G) {
-            const int cg = gcnt[tid];
-            int *cn = I.two_pass ? &I.coarse_n[(tid << I.log2SUB) + sub] : &I.slab_n[out_par][tid];
-            gbase[tid] = cg ? (i64)atomicAdd(cn, cg) : 0;
-        }
-        __syncthreads();
-        auto put = [&](int g, int rk, const T &dd, double vv, u32 k) {
-            const i64 pos = gbase[g] + rk;
-            if (I.two_pass) {
-                const i64 cs = ((i64)g << I.log2SUB) + sub;
-                if (pos < I.cap_c) store_rec<W>(I.coarse, cs * I.cap_c + pos, dd, vv);
-                else set_error(ctrl, FQE_CAP_SLAB, g);
+        if (nk > 0) { g0 = out.group(d0); rk0 = out.rank(g0); }
+        if (nk > 1) { g1 = out.group(d1); rk1 = out.rank(g1); }
+        if (nk > 2) { g2 = out.group(d2); rk2 = out.rank(g2); }
+        if (nk > 3) { g3 = out.group(d3); rk3 = out.rank(g3); }
+        out.reserve();
+        if (nk > 0) out.put(g0, rk0, d0, v0, a0, a1, k0);
+        if (nk > 1) out.put(g1, rk1, d1, v1, a0, a1, k0 + 1);
+        if (nk > 2) out.put(g2, rk2, d2, v2, a0, a1, k0 + 2);
+        if (nk > 3) out.put(g3, rk3, d3, v3, a0, a1, k0 + 3);
+    }
+}
+
+// Stochastic spawns (Sec. 3.2, matrix compression): ceil|c| attempts per
+// parent, each an independent draw.  The A attempts of the nS stochastic
+// entries (permuted indices w0_ .. w0_+nS-1, attempt offsets in info[2 w])
+// are enumerated flat: in each round thread t takes attempt base + t, finds
+// its parent by a binary search with a fixed number of steps and generates
+// one record with branch-free code, so all lanes of a wave do the same work.
+template <int W, int MODEL, int BS>
+__device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const int b, const int par,
+                                           const u32 spawn_step, const int w0_, const int nS, const u32 *info,
+                                           const u32 *perm, const i64 A)
+{
+    typedef typename AddrOf<W>::T T;
+    const int tid = threadIdx.x;
+    const SpawnOut<W> out(I, L, par);
+    int top = 1;
+    while (2 * top <= nS) top *= 2;
+    for (i64 base = 0; base < A; base += BS) {
+        out.begin();
+        const i64 kf = base + tid;
+        const bool act = kf < A;
+        T d = AddrOf<W>::make(0, 0);
+        double v = 0.0;
+        int g = 0, rk = 0;
+        u64 a0 = 0, a1 = 0;
+        u32 k = 0;
+        if (act) {
+            int lo = 0;
+            for (int stp = top; stp > 0; stp >>= 1) {
+                const int nx = lo + stp;
+                if (nx < nS && (i64)info[2 * (w0_ + nx)] <= kf) lo = nx;
+            }
+            const int w = w0_ + lo;
+            k = (u32)(kf - (i64)info[2 * w]);
+            const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
+            const i64 e = (i64)b * I.cap_t + perm[w];
+            a0 = I.tab_a[par][0][e];
+            a1 = W == 2 ? I.tab_a[par][1][e] : 0;
+            const double c = I.tab_v[par][e];
+            const T a = AddrOf<W>::make(a0, a1);
+            double h, q;
+            if (MODEL == 0) {
+                const R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
+                const u32 kk = k & 3;
+                const u32 rw = kk == 0 ? r.x : kk == 1 ? r.y : kk == 2 ? r.z : r.w;
+                const T st = run_starts(a);
+                const int o = popc(st);
+                d = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)(2 * o)), h);
+                q = (double)(2 * o) / (double)cnt;
             } else {
-                if (pos < I.cap_s) store_rec<W>(I.slab[out_par], (i64)g * I.cap_s + pos, dd, vv);
-                else set_error(ctrl, FQE_CAP_SLAB, g);
+                const R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
+                const bool odd = (k & 1) != 0;
+                i64 qn;
+                d = mom_stochastic(I.mc, a, odd ? r.z : r.x, odd ? r.w : r.y, h, qn);
+                q = (double)qn / (double)cnt;
             }
-            if (I.flags & 1) {
-                i64 di = atomicAdd((unsigned long long *)&ctrl->dump_spawn_n, 1ull);
-                if (di < I.dump_cap) {
-                    I.dsp_parent[di * W] = a0;
-                    if (W == 2) I.dsp_parent[di * W + 1] = a1;
-                    I.dsp_attempt[di] = (i64)k;
-                    I.dsp_dest[di * W] = word0(dd);
-                    if (W == 2) I.dsp_dest[di * W + 1] = word1(dd);
-                    I.dsp_val[di] = vv;
-                }
-            }
-        };
-        if (nk > 0) put(g0, rk0, d0, v0, k0);
-        if (nk > 1) put(g1, rk1, d1, v1, k0 + 1);
-        if (nk > 2) put(g2, rk2, d2, v2, k0 + 2);
-        if (nk > 3) put(g3, rk3, d3, v3, k0 + 3);
-        __syncthreads();
+            v = ((-(I.dtau * h)) * c) * q;
+            g = out.group(d);
+            rk = out.rank(g);
+        }
+        out.reserve();
+        if (act) out.put(g, rk, d, v, a0, a1, k);
     }
 }
 
@@ -762,23 +821,35 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
         sp.spawns = tot_sp;
         sp.pad = 0;
         I.spart[spawn_step & 1][b] = sp;
+        if (b == 0) ctrl->spawn_par = par;
     }
     __syncthreads();
-    i64 utot;
+    // offsets: units of 4 column entries for the exact entries, attempts for
+    // the stochastic ones, each counted from the first entry of its kind
+    i64 utot, atot;
     {
-        i64 units = 0;
-        for (int i = i0; i < i1; i++) units += ((info[2 * i + 1] & 0x7fffffffu) + 3) / 4;
-        i64 ubase = block_excl_scan<BS>(units, L.misc, utot);
+        i64 units = 0, atts = 0;
         for (int i = i0; i < i1; i++) {
-            info[2 * i] = (u32)ubase;
-            ubase += ((info[2 * i + 1] & 0x7fffffffu) + 3) / 4;
+            const i64 cnt = info[2 * i + 1] & 0x7fffffffu;
+            if (i < tot_e) units += (cnt + 3) / 4;
+            else atts += cnt;
         }
+        i64 ub = block_excl_scan<BS>(units, L.misc, utot);
+        i64 ab = block_excl_scan<BS>(atts, L.misc, atot);
+        for (int i = i0; i < i1; i++) {
+            const i64 cnt = info[2 * i + 1] & 0x7fffffffu;
+            if (i < tot_e) { info[2 * i] = (u32)ub; ub += (cnt + 3) / 4; }
+            else { info[2 * i] = (u32)ab; ab += cnt; }
+        }
+    }
+    if (utot >= ((i64)1 << 32) || atot >= ((i64)1 << 32)) {
+        if (tid == 0) set_error(ctrl, FQE_CAP_SLAB, b);
+        return;
     }
     __syncthreads();
     mark(6);
-    const i64 u_split = tot_e == 0 ? 0 : (tot_e < nS ? (i64)info[2 * tot_e] : utot);
-    spawn_units<W, MODEL, BS, true>(I, L, b, par, spawn_step, nS, info, perm, par, 0, u_split);
-    spawn_units<W, MODEL, BS, false>(I, L, b, par, spawn_step, nS, info, perm, par, u_split, utot);
+    spawn_exact<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, info, perm, utot);
+    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, nS - (int)tot_e, info, perm, atot);
     mark(7);
 }
 

@@ -50,13 +50,14 @@ def _ws(model=0, M=6, N=6, W=1, **kw):
     h = fq.Hamiltonian(model, M, N, 0, 1.0, 6.0)
     p = fq.Params(1e-3, 1e3, 0.08, 0.0016, 1.0, 1.0, 0, W, 0)
     lay = fq.Layout(kw.get("table", 1000), kw.get("spawn", 4000), kw.get("buckets", 0),
-                    kw.get("slots", 0), kw.get("block", 0), 0)
+                    kw.get("slots", 0), kw.get("block", 0), kw.get("spawn_block", 0))
     return fq.workspace_size(h, p, lay)
 
 
 def test_workspace_size_and_defaults():
     n, lay = _ws()
     assert n > 0 and lay.buckets >= 1 and lay.lds_slots == 4096 and lay.block == 1024
+    assert lay.spawn_block == 256
     n2, lay2 = _ws(table=10_000_000, spawn=40_000_000)
     assert n2 > n and lay2.buckets & (lay2.buckets - 1) == 0 and lay2.buckets > 1000
     n3, lay3 = _ws(model=1, M=16, N=16)
@@ -65,7 +66,7 @@ def test_workspace_size_and_defaults():
 
 @pytest.mark.parametrize("kw", [dict(M=1), dict(model=1, M=2, N=3), dict(M=40, N=30, W=1),
                                 dict(slots=3000), dict(block=128), dict(slots=8192, block=512),
-                                dict(buckets=3)])
+                                dict(buckets=3), dict(spawn_block=128), dict(spawn_block=2048)])
 def test_workspace_size_rejects_invalid(kw):
     with pytest.raises(fq.FqError):
         _ws(**kw)

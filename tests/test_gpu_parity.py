@@ -28,10 +28,12 @@ def _flush(*a):
 
 
 def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2048, block=512,
-             t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0):
+             t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0,
+             spawn_block=None):
     fq = _fq()
+    spawn_block = block if spawn_block is None else spawn_block
     _flush(f"[one_step] model={model} M={M} N={N} W={W} n={n_entries} B={buckets} "
-           f"slots={slots} block={block} t_rel={t_rel}")
+           f"slots={slots} block={block} spawn_block={spawn_block} t_rel={t_rel}")
     rng = np.random.default_rng(seed)
     occs = synthetic.random_occupations(rng, M, N, n_entries, momentum_sector=sector)
     vals = synthetic.random_amplitudes(rng, len(occs), lo=lo, hi=hi)
@@ -46,7 +48,7 @@ def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2
     s = fq.Solver(model, M, N, t=t, u=u, dtau=dtau, target_walkers=1e4, threshold=theta,
                   t_rel=t_rel, seed=seed + 99, addr_words=W, flags=3, table_capacity=cap_t,
                   spawn_capacity=max(8 * len(o["events"]), 65536), buckets=buckets,
-                  lds_slots=slots, block=block)
+                  lds_slots=slots, block=block, spawn_block=spawn_block)
     s.set_state(gaddr, vals, shift, step, ref=ref_g, yref=10.0)
     ev = s.spawn_dump()
     st = s.run(1)
@@ -146,12 +148,13 @@ def test_single_entry_state(orc):
     check_parity(*r)
 
 
-def _c1_gpu(steps, buckets=0, slots=0, block=0):
+def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0):
     fq = _fq()
     c = synthetic.CONFIGS["c1"]
     s = fq.Solver(c["model"], c["M"], c["N"], t=c["t"], u=c["u"], dtau=c["dtau"],
                   target_walkers=c["target"], seed=c["seed"], addr_words=1, table_capacity=1024,
-                  spawn_capacity=8192, buckets=buckets, lds_slots=slots, block=block)
+                  spawn_capacity=8192, buckets=buckets, lds_slots=slots, block=block,
+                  spawn_block=spawn_block)
     a = fq.start_address(c["model"], c["M"], c["N"])
     s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
     st = s.run(steps)
@@ -193,6 +196,7 @@ def test_c1_energy_within_3_sigma_of_ed(orc):
 def test_schedule_independence():
     """Bucket count, LDS table size and workgroup size do not change a bit."""
     ref = _c1_gpu(3000)
-    for B, slots, block in [(1, 1024, 256), (8, 1024, 1024), (64, 4096, 512), (2, 2048, 1024)]:
-        st = _c1_gpu(3000, B, slots, block)
-        assert st.tobytes() == ref.tobytes(), (B, slots, block)
+    for B, slots, block, sb in [(1, 1024, 256, 1024), (8, 1024, 1024, 256), (64, 4096, 512, 512),
+                                (2, 2048, 1024, 256), (128, 1024, 256, 256)]:
+        st = _c1_gpu(3000, B, slots, block, sb)
+        assert st.tobytes() == ref.tobytes(), (B, slots, block, sb)
