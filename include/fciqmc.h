@@ -179,6 +179,109 @@ int fq_get_layout(const fq_handle *q, fq_layout *layout);
 int fq_destroy(fq_handle *q);
 const char *fq_last_error(const fq_handle *q);
 
+/* ------------------------------------------------------------------------
+ * Copy and autotuning.
+ *
+ * fq_copy_state copies the current state of `src` (vector, shift, step,
+ * reference vector) into `dst`, on the device, with no host round trip.  The
+ * two handles must have the same Hamiltonian and parameters; their layouts
+ * may differ.  Because the step is layout independent, `dst` then continues
+ * exactly as `src` would.
+ *
+ * fq_autotune times candidate layouts (the hash and tile shapes: buckets,
+ * LDS slots, merge and spawn workgroup sizes) on a copy of the state of
+ * `src`: for each of the n candidates it creates a handle in `scratch`
+ * (caller-owned device memory), copies the state, runs `trial_steps` steps
+ * and records the mean milliseconds per step from HIP events in ms[i]
+ * (negative when the candidate does not fit `scratch` or fails).  *best is
+ * the index of the fastest candidate.  `src` is not modified.
+ * ------------------------------------------------------------------------ */
+int fq_copy_state(fq_handle *dst, fq_handle *src, void *stream);
+int fq_autotune(fq_handle *src, const fq_layout *candidates, int32_t n, int32_t trial_steps, void *scratch,
+                size_t scratch_bytes, double *ms, int32_t *best, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batch: n independent instances advanced together, one launch per kernel
+ * per step for the whole batch (each workgroup finds its instance and bucket
+ * from a map), with per-instance tables, shifts and statistics.  Instances
+ * may differ in Hamiltonian (M, N, t, u), parameters and capacities; they
+ * must share the model kind (real space, momentum space with M <= 16 or
+ * M <= 32), addr_words, lds_slots, block and spawn_block.  Every instance
+ * produces the same results as it would alone.
+ *
+ * fq_batch_workspace_size: bytes of the single workspace for the batch
+ * (hams, params, layouts: arrays of n).  fq_batch_create carves it (caller
+ * owned, 256-byte aligned).  fq_batch_instance returns instance i's handle,
+ * owned by the batch, for fq_set_state, fq_get_state and the dumps (not for
+ * fq_destroy).  fq_batch_run advances every instance by n_steps steps;
+ * stats (host, may be NULL) receives n * n_steps rows, instance-major
+ * (row k of instance i at i * n_steps + k).  When an instance fails, the
+ * batch stops at the end of the chunk of steps in which it failed, every
+ * instance stays at its last completed step (completed rows are filled), the
+ * call returns that instance's status, and fq_batch_failed() names it.
+ * ------------------------------------------------------------------------ */
+typedef struct fq_batch fq_batch;
+int fq_batch_workspace_size(int32_t n, const fq_hamiltonian *hams, const fq_params *params,
+                            const fq_layout *layouts, size_t *bytes);
+int fq_batch_create(int32_t n, const fq_hamiltonian *hams, const fq_params *params, const fq_layout *layouts,
+                    void *workspace, size_t bytes, fq_batch **out);
+int fq_batch_instance(fq_batch *b, int32_t i, fq_handle **out);
+int fq_batch_run(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *stream);
+int32_t fq_batch_failed(const fq_batch *b);
+int fq_batch_destroy(fq_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Server: continuous batching of FCIQMC solves on one GPU.
+ *
+ * A request (Hamiltonian, parameters, capacities, start address with its
+ * walker number, step count) is queued by fq_server_submit.  Each call of
+ * fq_server_tick first admits queued requests in arrival order while the
+ * walker-table pool (the caller-owned device memory given at creation, the
+ * HBM budget) has room for the request's workspace and fewer than
+ * max_active solves are resident; then it advances every resident solve by
+ * steps_per_tick steps in one batch (a solve stops exactly at its step
+ * count); then it retires finished solves and frees their memory.  State
+ * stays resident on the device between ticks.  A solve's results do not
+ * depend on what else is in the batch.
+ *
+ * Solves start from `start_val` walkers on `start` with shift 0 and use
+ * y = start_val e_start for the projected energy (Sec. 2.1, Sec. 4.2).
+ * fq_server_poll reports a request's state, its last statistics row and the
+ * means of shift, y.Hc and y.c over the steps after the first half.  All
+ * requests of one server share the model, addr_words, lds_slots, block and
+ * spawn_block of its configuration (momentum space: M <= 16).  Not thread
+ * safe.
+ * ------------------------------------------------------------------------ */
+typedef struct fq_server fq_server;
+typedef struct {
+    int32_t model, addr_words;               /* every request uses these        */
+    int32_t lds_slots, block, spawn_block;   /* layout shared by the batch      */
+    int32_t max_active;                      /* resident solves at most         */
+    int64_t steps_per_tick;                  /* 1 .. 4096                       */
+} fq_server_config;
+
+#define FQ_REQ_QUEUED 0
+#define FQ_REQ_RUNNING 1
+#define FQ_REQ_DONE 2
+#define FQ_REQ_FAILED 3
+
+typedef struct {
+    int32_t state, status;      /* FQ_REQ_*; fq_status of a failed request  */
+    int64_t steps_done;
+    fq_step_stats last;         /* last completed row                       */
+    double mean_shift, mean_hproj, mean_vproj;  /* over steps > n_steps / 2 */
+    int64_t n_mean;
+    int64_t workspace_bytes;
+} fq_request_info;
+
+int fq_server_create(const fq_server_config *cfg, void *pool, size_t pool_bytes, fq_server **out);
+int fq_server_submit(fq_server *sv, const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout,
+                     const uint64_t *start, double start_val, int64_t n_steps, uint64_t *request_id);
+int fq_server_tick(fq_server *sv, void *stream, int32_t *active, int32_t *queued, int32_t *finished);
+int fq_server_poll(fq_server *sv, uint64_t request_id, fq_request_info *info);
+int fq_server_destroy(fq_server *sv);
+const char *fq_server_last_error(const fq_server *sv);
+
 /* Host helper: occupations -> W address words (the encoding of Sec. 6.1). */
 int fq_encode(const int32_t *occ, int32_t M, int32_t W, uint64_t *out);
 

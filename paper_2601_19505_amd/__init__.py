@@ -55,6 +55,20 @@ class StepStats(C.Structure):
                 ("norm", C.c_double), ("hproj", C.c_double), ("vproj", C.c_double)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("model", C.c_int32), ("addr_words", C.c_int32), ("lds_slots", C.c_int32),
+                ("block", C.c_int32), ("spawn_block", C.c_int32), ("max_active", C.c_int32),
+                ("steps_per_tick", C.c_int64)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int64),
+                ("last", StepStats), ("mean_shift", C.c_double), ("mean_hproj", C.c_double),
+                ("mean_vproj", C.c_double), ("n_mean", C.c_int64), ("workspace_bytes", C.c_int64)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
 STATS_DTYPE = np.dtype([("step", np.int64), ("len", np.int64), ("exact_steps", np.int64),
                         ("inexact_steps", np.int64), ("spawns", np.int64), ("shift", np.float64),
                         ("norm", np.float64), ("hproj", np.float64), ("vproj", np.float64)])
@@ -97,6 +111,24 @@ def lib():
             "fq_debug_counters": (C.c_int, [vp, f64p, C.c_int32, C.c_int32, vp]),
             "fq_destroy": (C.c_int, [vp]),
             "fq_last_error": (C.c_char_p, [vp]),
+            "fq_copy_state": (C.c_int, [vp, vp, vp]),
+            "fq_autotune": (C.c_int, [vp, P(Layout), C.c_int32, C.c_int32, vp, C.c_size_t, f64p,
+                                      i32p, vp]),
+            "fq_batch_workspace_size": (C.c_int, [C.c_int32, P(Hamiltonian), P(Params), P(Layout),
+                                                  P(C.c_size_t)]),
+            "fq_batch_create": (C.c_int, [C.c_int32, P(Hamiltonian), P(Params), P(Layout), vp,
+                                          C.c_size_t, P(vp)]),
+            "fq_batch_instance": (C.c_int, [vp, C.c_int32, P(vp)]),
+            "fq_batch_run": (C.c_int, [vp, C.c_int64, vp, vp]),
+            "fq_batch_failed": (C.c_int32, [vp]),
+            "fq_batch_destroy": (C.c_int, [vp]),
+            "fq_server_create": (C.c_int, [P(ServerConfig), vp, C.c_size_t, P(vp)]),
+            "fq_server_submit": (C.c_int, [vp, P(Hamiltonian), P(Params), P(Layout), u64p, C.c_double,
+                                           C.c_int64, P(C.c_uint64)]),
+            "fq_server_tick": (C.c_int, [vp, vp, i32p, i32p, i32p]),
+            "fq_server_poll": (C.c_int, [vp, C.c_uint64, P(RequestInfo)]),
+            "fq_server_destroy": (C.c_int, [vp]),
+            "fq_server_last_error": (C.c_char_p, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -141,6 +173,19 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _ham_params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08, xi=None,
+                threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0):
+    if xi is None:
+        xi = zeta * zeta / 4.0
+    return (Hamiltonian(model, M, N, 0, float(t), float(u)),
+            Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words, flags))
+
+
+def _layout(table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0,
+            spawn_block=0):
+    return Layout(table_capacity, spawn_capacity, buckets, lds_slots, block, spawn_block)
+
+
 class Solver:
     """One FCIQMC instance on the current GPU (plain per-step launches)."""
 
@@ -151,15 +196,12 @@ class Solver:
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the FCIQMC solver needs a GPU")
-        if xi is None:
-            xi = zeta * zeta / 4.0
-        self.ham = Hamiltonian(model, M, N, 0, float(t), float(u))
-        self.params = Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words,
-                             flags)
+        self.ham, self.params = _ham_params(model, M, N, t, u, dtau, target_walkers, zeta, xi,
+                                            threshold, t_rel, seed, addr_words, flags)
         self.W = addr_words
         nbytes, lay = workspace_size(self.ham, self.params,
-                                     Layout(table_capacity, spawn_capacity, buckets, lds_slots,
-                                            block, spawn_block))
+                                     _layout(table_capacity, spawn_capacity, buckets, lds_slots,
+                                             block, spawn_block))
         self.layout = lay
         self.nbytes = nbytes
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -287,6 +329,194 @@ class Solver:
         lo = Layout()
         self._check(lib().fq_get_layout(self.h, C.byref(lo)), "fq_get_layout")
         return lo
+
+    def copy_state_from(self, other):
+        """Copy the state of another solver (same Hamiltonian and parameters,
+        any layout) on the device."""
+        self._check(lib().fq_copy_state(self.h, other.h, _stream()), "fq_copy_state")
+
+    def autotune(self, candidates, trial_steps=20):
+        """Time candidate layouts (dicts of buckets, lds_slots, block,
+        spawn_block; capacities default to this solver's) on copies of this
+        solver's state.  Returns (ms per step for each candidate, or -1,
+        index of the fastest)."""
+        lays = (Layout * len(candidates))()
+        need = 0
+        for i, c in enumerate(candidates):
+            lays[i] = _layout(c.get("table_capacity", self.table_capacity),
+                              c.get("spawn_capacity", self.spawn_capacity), c.get("buckets", 0),
+                              c.get("lds_slots", 0), c.get("block", 0), c.get("spawn_block", 0))
+            try:
+                need = max(need, workspace_size(self.ham, self.params, lays[i])[0])
+            except FqError:
+                pass
+        import torch
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        ms = np.zeros(len(candidates))
+        best = C.c_int32(-1)
+        self._check(lib().fq_autotune(self.h, lays, len(candidates), int(trial_steps),
+                                      C.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                      _p(ms, C.c_double), C.byref(best), _stream()), "fq_autotune")
+        del scratch
+        return ms, best.value
+
+
+class _Borrowed(Solver):
+    """Handle owned by a batch: same calls as a Solver, no ownership."""
+
+    def __init__(self, h, W, ham, params, table_capacity, spawn_capacity):
+        self.h = h
+        self.W = W
+        self.ham = ham
+        self.params = params
+        self.table_capacity = table_capacity
+        self.spawn_capacity = spawn_capacity
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """n instances advanced together (one launch per kernel per step).
+
+    `specs` is a list of dicts with the keyword arguments of Solver (model,
+    M, N, t, u, dtau, target_walkers, seed, addr_words, threshold, t_rel,
+    table_capacity, spawn_capacity, buckets, lds_slots, block, spawn_block).
+    """
+
+    def __init__(self, specs):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the FCIQMC batch needs a GPU")
+        n = len(specs)
+        self.n = n
+        self.hams = (Hamiltonian * n)()
+        self.params = (Params * n)()
+        self.layouts = (Layout * n)()
+        lay_keys = ("table_capacity", "spawn_capacity", "buckets", "lds_slots", "block",
+                    "spawn_block")
+        for i, sp in enumerate(specs):
+            hp = {k: v for k, v in sp.items() if k not in lay_keys}
+            h, p = _ham_params(**hp)
+            self.hams[i], self.params[i] = h, p
+            self.layouts[i] = _layout(**{k: v for k, v in sp.items() if k in lay_keys})
+        nb = C.c_size_t(0)
+        rc = lib().fq_batch_workspace_size(n, self.hams, self.params, self.layouts, C.byref(nb))
+        if rc:
+            raise FqError(rc, f"fq_batch_workspace_size: {lib().fq_last_error(None).decode()}")
+        self.nbytes = nb.value
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device="cuda")
+        b = C.c_void_p()
+        rc = lib().fq_batch_create(n, self.hams, self.params, self.layouts,
+                                   C.c_void_p(self.ws.data_ptr()), self.nbytes, C.byref(b))
+        if rc:
+            raise FqError(rc, f"fq_batch_create: {lib().fq_last_error(None).decode()}")
+        self.b = b
+        self._inst = []
+        for i in range(n):
+            h = C.c_void_p()
+            rc = lib().fq_batch_instance(self.b, i, C.byref(h))
+            if rc:
+                raise FqError(rc, "fq_batch_instance")
+            lo = Layout()
+            lib().fq_get_layout(h, C.byref(lo))
+            self._inst.append(_Borrowed(h, self.params[i].addr_words, self.hams[i], self.params[i],
+                                        lo.table_capacity, lo.spawn_capacity))
+
+    def instance(self, i):
+        return self._inst[i]
+
+    def run(self, n_steps):
+        """Advance every instance; returns statistics of shape (n, n_steps)."""
+        out = np.zeros((self.n, n_steps), STATS_DTYPE)
+        rc = lib().fq_batch_run(self.b, n_steps, C.c_void_p(out.ctypes.data), _stream())
+        if rc:
+            i = lib().fq_batch_failed(self.b)
+            msg = lib().fq_last_error(self._inst[i].h).decode() if i >= 0 else ""
+            err = FqError(rc, f"fq_batch_run: instance {i}: {msg}")
+            err.stats = out
+            err.instance = i
+            raise err
+        return out
+
+    def close(self):
+        if getattr(self, "b", None):
+            for x in self._inst:
+                x.close()
+            lib().fq_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous batching of FCIQMC solves (fq_server_* of the C ABI)."""
+
+    def __init__(self, model, pool_bytes, addr_words=1, lds_slots=1024, block=256, spawn_block=256,
+                 max_active=64, steps_per_tick=200):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the FCIQMC server needs a GPU")
+        self.cfg = ServerConfig(model, addr_words, lds_slots, block, spawn_block, max_active,
+                                steps_per_tick)
+        self.W = addr_words
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device="cuda")
+        sv = C.c_void_p()
+        rc = lib().fq_server_create(C.byref(self.cfg), C.c_void_p(self.pool.data_ptr()),
+                                    self.pool.numel(), C.byref(sv))
+        if rc:
+            raise FqError(rc, f"fq_server_create: {lib().fq_server_last_error(None).decode()}")
+        self.sv = sv
+
+    def _check(self, rc, what):
+        if rc:
+            raise FqError(rc, f"{what}: {lib().fq_server_last_error(self.sv).decode()}")
+
+    def submit(self, spec, start, start_val=10.0, n_steps=1000):
+        lay_keys = ("table_capacity", "spawn_capacity", "buckets", "lds_slots", "block",
+                    "spawn_block")
+        hp = {k: v for k, v in spec.items() if k not in lay_keys}
+        hp.setdefault("addr_words", self.W)
+        h, p = _ham_params(**hp)
+        lay = _layout(**{k: v for k, v in spec.items() if k in lay_keys})
+        a = np.zeros(2, np.uint64)
+        st = np.asarray(start, dtype=np.uint64).ravel()
+        a[:len(st)] = st
+        rid = C.c_uint64(0)
+        self._check(lib().fq_server_submit(self.sv, C.byref(h), C.byref(p), C.byref(lay),
+                                           _p(a, C.c_uint64), float(start_val), int(n_steps),
+                                           C.byref(rid)), "fq_server_submit")
+        return rid.value
+
+    def tick(self):
+        a, q, f = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        self._check(lib().fq_server_tick(self.sv, _stream(), C.byref(a), C.byref(q), C.byref(f)),
+                    "fq_server_tick")
+        return a.value, q.value, f.value
+
+    def poll(self, rid):
+        info = RequestInfo()
+        self._check(lib().fq_server_poll(self.sv, int(rid), C.byref(info)), "fq_server_poll")
+        last = {k: getattr(info.last, k) for k, _ in StepStats._fields_}
+        return dict(state=info.state, status=info.status, steps_done=info.steps_done, last=last,
+                    mean_shift=info.mean_shift, mean_hproj=info.mean_hproj,
+                    mean_vproj=info.mean_vproj, n_mean=info.n_mean,
+                    workspace_bytes=info.workspace_bytes)
+
+    def close(self):
+        if getattr(self, "sv", None):
+            lib().fq_server_destroy(self.sv)
+            self.sv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def start_address(model, M, N, W=1):

@@ -17,6 +17,10 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 
 #include "fciqmc.h"
 #include "fq_step.hpp"
@@ -24,33 +28,85 @@
 using namespace fq;
 
 // ------------------------------------------------------------------ kernels
+//
+// The step kernels run over a set of instances: one, or a batch.  `insts` is
+// a device array of instance descriptors.  A merge or spawn workgroup finds
+// its instance and bucket through `map` (entry = instance << 14 | bucket);
+// without a map there is one instance and workgroup b takes bucket b.
 
-template <int W, int MODEL, int BS>
-__global__ __launch_bounds__(BS) void k_merge(const Inst *I)
+__device__ __forceinline__ const Inst &locate(const Inst *const *insts, const u32 *map, int &b)
 {
-    extern __shared__ __align__(16) char smem[];
-    merge_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, smem);
+    if (map) {
+        const u32 m = map[blockIdx.x];
+        b = (int)(m & 0x3fffu);
+        return *insts[m >> 14];
+    }
+    b = (int)blockIdx.x;
+    return *insts[0];
 }
 
 template <int W, int MODEL, int BS>
-__global__ __launch_bounds__(BS) void k_spawn(const Inst *I, int mode)
+__global__ __launch_bounds__(BS) void k_merge(const Inst *const *insts, const u32 *map)
 {
     extern __shared__ __align__(16) char smem[];
-    spawn_bucket<W, MODEL, BS>(*I, (int)blockIdx.x, mode, smem);
+    int b;
+    const Inst &I = locate(insts, map, b);
+    merge_bucket<W, MODEL, BS>(I, b, smem);
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(const Inst *I) { finalize_instance<1024>(*I); }
-
-// Workgroups are dispatched round-robin over the 8 XCDs (blockIdx mod 8).
-// All sub-slabs of one group go to the same XCD, so the runs that different
-// workgroups append to one bucket's slab meet in that XCD's L2 and partial
-// cache lines are merged before they are written back.
-template <int W> __global__ __launch_bounds__(1024) void k_part(const Inst *I)
+template <int W, int MODEL, int BS>
+__global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u32 *map, int mode)
 {
-    const int x = (int)blockIdx.x, xcd = x & 7, j = x >> 3;
-    const int g = ((j >> I->log2SUB) << 3) | xcd;
-    const int sub = j & ((1 << I->log2SUB) - 1);
-    partition_coarse<W, 1024, 8>(*I, (g << I->log2SUB) | sub);
+    extern __shared__ __align__(16) char smem[];
+    int b;
+    const Inst &I = locate(insts, map, b);
+    spawn_bucket<W, MODEL, BS>(I, b, mode, smem);
+}
+
+// one workgroup per instance
+__global__ __launch_bounds__(1024) void k_finalize(const Inst *const *insts)
+{
+    finalize_instance<1024>(*insts[blockIdx.x]);
+}
+
+// Second partition pass; map entry = instance << 14 | coarse sub-slab.  The
+// host orders the entries so that all sub-slabs of one coarse group run on
+// the same XCD (workgroups are dispatched round-robin over the 8 XCDs): the
+// runs that different workgroups append to one bucket's slab then meet in
+// that XCD's L2, which merges partial cache lines before they are written
+// back.
+template <int W> __global__ __launch_bounds__(1024) void k_part(const Inst *const *insts, const u32 *map)
+{
+    const u32 m = map[blockIdx.x];
+    partition_coarse<W, 1024, 8>(*insts[m >> 14], (int)(m & 0x3fffu));
+}
+
+// start of a chunk of steps: statistics rows are stored from row 0
+__global__ void k_begin_chunk(const Inst *const *insts, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        Ctrl *c = insts[i]->ctrl;
+        c->ring_base = c->step + 1;
+    }
+}
+
+// every instance stops after `steps` more steps
+__global__ void k_set_stop(const Inst *const *insts, int n, i64 steps)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        Ctrl *c = insts[i]->ctrl;
+        c->stop_step = c->step + steps;
+    }
+}
+
+// copy the control blocks of n instances into one array
+__global__ void k_gather_ctrl(const Inst *const *insts, int n, Ctrl *out)
+{
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const u32 *src = (const u32 *)insts[i]->ctrl;
+        u32 *dst = (u32 *)(out + i);
+        for (int k = threadIdx.x; k < (int)(sizeof(Ctrl) / 4); k += blockDim.x) dst[k] = src[k];
+    }
 }
 
 // insert host-staged entries into table[parity] and accumulate the norm
@@ -217,11 +273,24 @@ size_t lds_bytes(int W, int slots)
 size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8; }
 
 constexpr size_t LDS_MAX = 160 * 1024;
+static_assert(sizeof(Ctrl) % 4 == 0, "Ctrl is copied in 32-bit words");
+
+// A set of instances stepped together: one launch per kernel per step.
+struct Exec {
+    int W = 1, var = 0, block = 512, spawn_block = 256;
+    size_t lds_m = 0, lds_s = 0;  // dynamic LDS of the merge and spawn kernels
+    int n = 0;                    // instances
+    const Inst *const *insts = nullptr;
+    const u32 *map = nullptr;     // merge / spawn workgroup map (nullptr: one instance)
+    int grid = 0;
+    const u32 *pmap = nullptr;    // second-pass partition map
+    int pgrid = 0;
+};
 
 struct Resolved {
     int W, nb, B, log2B, slots, block, spawn_block, two_pass, log2G, log2SUB;
     i64 cap_t, cap_s, cap_c, dump_cap;
-    size_t off_ctrl, off_inst, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
+    size_t off_ctrl, off_inst, off_iptr, off_pmap, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
         off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], off_coarse,
         off_coarse_n, total;
@@ -306,6 +375,8 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     R.off_ctrl = take(sizeof(Ctrl));
     R.off_inst = take(sizeof(Inst));
+    R.off_iptr = take(sizeof(Inst *));
+    R.off_pmap = take(sizeof(u32) << (R.log2G + R.log2SUB));
     R.off_sq = take(sizeof(double) * R.nsq);
     R.off_eps = take(sizeof(double) * MOM_MAXM);
     R.off_ref_a = take(sizeof(u64) * 2 * REFCAP);
@@ -340,6 +411,72 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     return FQ_OK;
 }
 
+// The dynamic-LDS limit is a property of the kernel, shared by every handle
+// in the process: only ever raise it, to the largest size any handle needs.
+hipError_t ensure_lds(const void *kf, size_t bytes)
+{
+    static std::mutex mu;
+    static std::map<const void *, size_t> limit;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &cur = limit[kf];
+    if (bytes <= cur) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
+}
+
+// Entries of the second-pass map for instance `inst` whose first workgroup
+// is a multiple of 8: local workgroup x runs on XCD x mod 8 and takes coarse
+// group ((x / 8) / 64) * 8 + x mod 8, sub-slab (x / 8) mod 64, so the 64
+// sub-slabs of a group share one XCD.  Needs at least 8 groups.
+void append_pmap(const Resolved &R, u32 inst, std::vector<u32> &out)
+{
+    if (!R.two_pass) return;
+    const int nblk = 1 << (R.log2G + R.log2SUB);
+    for (int x = 0; x < nblk; x++) {
+        const int xcd = x & 7, j = x >> 3;
+        const int g = ((j >> R.log2SUB) << 3) | xcd;
+        const int sub = j & ((1 << R.log2SUB) - 1);
+        out.push_back((inst << 14) | (u32)((g << R.log2SUB) | sub));
+    }
+}
+
+hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s)
+{
+    const void *kf = step_kernel(X.W, X.var, X.spawn_block, true);
+    void *args[] = {(void *)&X.insts, (void *)&X.map, (void *)&mode};
+    hipError_t e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.spawn_block), args, X.lds_s, s);
+    if (e == hipSuccess && X.pgrid > 0) {
+        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(1024), 0, s, X.insts, X.pmap);
+        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(1024), 0, s, X.insts, X.pmap);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// one step of every instance of X: merge, spawn (+ partition), finalize;
+// with `ev`, events before the merge, after the merge, after the spawn and
+// partition, and after the finalize
+hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev)
+{
+    hipError_t e = hipSuccess;
+    if (ev) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess) {
+        const void *kf = step_kernel(X.W, X.var, X.block, false);
+        void *args[] = {(void *)&X.insts, (void *)&X.map};
+        e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.block), args, X.lds_m, s);
+    }
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = launch_spawn(X, 0, s);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_finalize, dim3(X.n), dim3(1024), 0, s, X.insts);
+        e = hipGetLastError();
+    }
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
+    return e;
+}
+
 }  // namespace
 
 struct fq_handle {
@@ -351,6 +488,9 @@ struct fq_handle {
     Inst inst;      // host copy
     Inst *d_inst;
     Ctrl *d_ctrl;
+    Exec X;         // this instance alone
+    uint64_t ref[2];
+    double yref;
     int have_state;
     i64 step;
     int parity;
@@ -380,6 +520,8 @@ static int hip_fail(fq_handle *q, hipError_t e, const char *what)
     } while (0)
 
 static int read_ctrl(fq_handle *q, Ctrl &c, hipStream_t s);
+static int load_state(fq_handle *q, const u64 *sa, const double *sv, i64 n, double shift, i64 step,
+                      const uint64_t *ref_addr, double ref_val, hipStream_t s);
 
 static const char *fqe_name(int e)
 {
@@ -526,11 +668,29 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl));
+    const Inst *iptr = q->d_inst;
+    if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_iptr, &iptr, sizeof iptr, hipMemcpyHostToDevice);
+    std::vector<u32> pm;
+    append_pmap(R, 0, pm);
+    if (e == hipSuccess && !pm.empty())
+        e = hipMemcpy(q->ws + R.off_pmap, pm.data(), sizeof(u32) * pm.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: workspace initialisation"); delete q; return FQ_EHIP; }
-    e = hipFuncSetAttribute(km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(R.W, R.slots));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_spawn_bytes(R.cap_t));
+    e = ensure_lds(km, lds_bytes(R.W, R.slots));
+    if (e == hipSuccess) e = ensure_lds(ks, lds_spawn_bytes(R.cap_t));
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
+    Exec &X = q->X;
+    X.W = R.W;
+    X.var = variant(h->model, h->M);
+    X.block = R.block;
+    X.spawn_block = R.spawn_block;
+    X.lds_m = lds_bytes(R.W, R.slots);
+    X.lds_s = lds_spawn_bytes(R.cap_t);
+    X.n = 1;
+    X.insts = (const Inst *const *)(q->ws + R.off_iptr);
+    X.map = nullptr;
+    X.grid = R.B;
+    X.pmap = (const u32 *)(q->ws + R.off_pmap);
+    X.pgrid = (int)pm.size();
     q->ring_host.resize(RING);
     *out = q;
     return FQ_OK;
@@ -576,36 +736,6 @@ int fq_get_layout(const fq_handle *q, fq_layout *layout)
 {
     if (!q || !layout) return FQ_EINVAL;
     *layout = q->L;
-    return FQ_OK;
-}
-
-static int launch_merge(fq_handle *q, hipStream_t s)
-{
-    const Resolved &R = q->R;
-    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.block, false);
-    void *args[] = {(void *)&q->d_inst};
-    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.block), args, lds_bytes(R.W, R.slots), s));
-    return FQ_OK;
-}
-
-// mode 0: spawns of the table the merge just wrote; mode 1: of a state that was set
-static int launch_spawn(fq_handle *q, int mode, hipStream_t s)
-{
-    const Resolved &R = q->R;
-    const void *kf = step_kernel(R.W, variant(q->h.model, q->h.M), R.spawn_block, true);
-    void *args[] = {(void *)&q->d_inst, (void *)&mode};
-    HIPCHK(q, hipLaunchKernel(kf, dim3(R.B), dim3(R.spawn_block), args, lds_spawn_bytes(R.cap_t), s));
-    return FQ_OK;
-}
-
-static int launch_partition(fq_handle *q, hipStream_t s)
-{
-    const Resolved &R = q->R;
-    if (!R.two_pass) return FQ_OK;
-    const int nblk = 1 << (R.log2G + R.log2SUB);
-    if (R.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(nblk), dim3(1024), 0, s, (const Inst *)q->d_inst);
-    else hipLaunchKernelGGL(k_part<2>, dim3(nblk), dim3(1024), 0, s, (const Inst *)q->d_inst);
-    HIPCHK(q, hipGetLastError());
     return FQ_OK;
 }
 
@@ -659,6 +789,22 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
         q->err = "state larger than the workspace capacity";
         return FQ_ECAPACITY;
     }
+    // stage entries in the parity-1 slab, then build the instance from them
+    u64 *sa = (u64 *)q->inst.slab[1];
+    double *sv = (double *)(q->inst.slab[1] + sizeof(u64) * W * n);
+    HIPCHK(q, hipMemcpyAsync(sa, addrs, sizeof(u64) * W * n, hipMemcpyHostToDevice, s));
+    HIPCHK(q, hipMemcpyAsync(sv, vals, sizeof(double) * n, hipMemcpyHostToDevice, s));
+    return load_state(q, sa, sv, n, shift, step, ref_addr, ref_val, s);
+}
+
+// State c^(step) from device arrays (n entries staged in the parity-1 slab
+// region or elsewhere outside the tables), shift, reference vector: insert
+// into table[0], reference column, spawns of c^(step) for step+1.
+static int load_state(fq_handle *q, const u64 *sa, const double *sv, i64 n, double shift, i64 step,
+                      const uint64_t *ref_addr, double ref_val, hipStream_t s)
+{
+    const Resolved &R = q->R;
+    const int W = R.W;
     // fresh control block
     Ctrl c;
     memset(&c, 0, sizeof c);
@@ -666,17 +812,13 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
     c.parity = 0;
     c.shift = shift;
     c.ring_base = step + 1;
+    c.stop_step = INT64_MAX;
     HIPCHK(q, hipMemcpyAsync(q->d_ctrl, &c, sizeof c, hipMemcpyHostToDevice, s));
     for (int k = 0; k < 2; k++) {
         HIPCHK(q, hipMemsetAsync(q->inst.tab_n[k], 0, sizeof(int) * R.B, s));
         HIPCHK(q, hipMemsetAsync(q->inst.slab_n[k], 0, sizeof(int) * R.B, s));
     }
     HIPCHK(q, hipMemsetAsync(q->inst.coarse_n, 0, sizeof(int) << (R.log2G + R.log2SUB), s));
-    // stage entries in the parity-1 slab, insert into table[0]
-    u64 *sa = (u64 *)q->inst.slab[1];
-    double *sv = (double *)(q->inst.slab[1] + sizeof(u64) * W * n);
-    HIPCHK(q, hipMemcpyAsync(sa, addrs, sizeof(u64) * W * n, hipMemcpyHostToDevice, s));
-    HIPCHK(q, hipMemcpyAsync(sv, vals, sizeof(double) * n, hipMemcpyHostToDevice, s));
     int grid = (int)std::min<i64>((n + 255) / 256, 4096);
     if (W == 1) hipLaunchKernelGGL(k_insert<1>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, (const u64 *)sa, (const double *)sv, (i64)n);
     else hipLaunchKernelGGL(k_insert<2>, dim3(grid), dim3(256), 0, s, (const Inst *)q->d_inst, (const u64 *)sa, (const double *)sv, (i64)n);
@@ -728,11 +870,9 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
     HIPCHK(q, hipMemcpy(q->inst.ref_off, off.data(), sizeof(int) * (R.B + 1), hipMemcpyHostToDevice));
     HIPCHK(q, hipMemcpy(q->d_inst, &q->inst, sizeof(Inst), hipMemcpyHostToDevice));
     // spawns of c^(step) for step+1
-    int rc = launch_spawn(q, 1, s);
-    if (rc) return rc;
-    rc = launch_partition(q, s);
-    if (rc) return rc;
+    HIPCHK(q, launch_spawn(q->X, 1, s));
     Ctrl cc;
+    int rc;
     rc = read_ctrl(q, cc, s);
     if (rc) return rc;
     if (cc.error) {
@@ -742,6 +882,9 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
     q->have_state = 1;
     q->step = step;
     q->parity = 0;
+    q->ref[0] = ref_addr[0];
+    q->ref[1] = W == 2 ? ref_addr[1] : 0;
+    q->yref = ref_val;
     return FQ_OK;
 }
 
@@ -774,29 +917,17 @@ int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream
         hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->dump_spawn_n, (i64)0);
         hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->dump_merged_n, (i64)0);
     }
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(64), 0, s, q->X.insts, 1, (i64)n_steps);
     i64 done = 0;
     while (done < n_steps) {
         const i64 chunk = std::min<i64>(RING, n_steps - done);
-        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &q->d_ctrl->ring_base, (i64)(q->step + 1));
+        hipLaunchKernelGGL(k_begin_chunk, dim3(1), dim3(64), 0, s, q->X.insts, 1);
         if (q->timing && (i64)q->ev.size() < NEV * chunk) {
             size_t old = q->ev.size();
             q->ev.resize(NEV * chunk);
             for (size_t k = old; k < q->ev.size(); k++) HIPCHK(q, hipEventCreate(&q->ev[k]));
         }
-        for (i64 k = 0; k < chunk; k++) {
-            hipEvent_t *ev = q->timing ? &q->ev[NEV * k] : nullptr;
-            if (ev) HIPCHK(q, hipEventRecord(ev[0], s));
-            int rc = launch_merge(q, s);
-            if (rc) return rc;
-            if (ev) HIPCHK(q, hipEventRecord(ev[1], s));
-            rc = launch_spawn(q, 0, s);
-            if (rc) return rc;
-            if (ev) HIPCHK(q, hipEventRecord(ev[2], s));
-            rc = launch_partition(q, s);
-            if (rc) return rc;
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, (const Inst *)q->d_inst);
-            if (ev) HIPCHK(q, hipEventRecord(ev[3], s));
-        }
+        for (i64 k = 0; k < chunk; k++) HIPCHK(q, exec_step(q->X, s, q->timing ? &q->ev[NEV * k] : nullptr));
         Ctrl c;
         int rc = read_ctrl(q, c, s);
         if (rc) return rc;
@@ -902,6 +1033,587 @@ int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap
         HIPCHK(q, hipMemcpy(addr, q->inst.dmg_addr, sizeof(u64) * W * k, hipMemcpyDeviceToHost));
         HIPCHK(q, hipMemcpy(value, q->inst.dmg_val, sizeof(double) * k, hipMemcpyDeviceToHost));
     }
+    return FQ_OK;
+}
+
+// ------------------------------------------------------------------ copy and autotuning
+
+int fq_copy_state(fq_handle *dst, fq_handle *src, void *stream)
+{
+    if (!dst || !src || dst == src) return FQ_EINVAL;
+    if (!src->have_state) { dst->err = "copy_state: source has no state"; return FQ_EINVAL; }
+    const fq_hamiltonian &a = dst->h, &b = src->h;
+    const fq_params &x = dst->p, &y = src->p;
+    if (a.model != b.model || a.M != b.M || a.N != b.N || a.t != b.t || a.u != b.u || x.dtau != y.dtau ||
+        x.target_walkers != y.target_walkers || x.zeta != y.zeta || x.xi != y.xi || x.threshold != y.threshold ||
+        x.t_rel != y.t_rel || x.seed != y.seed || x.addr_words != y.addr_words) {
+        dst->err = "copy_state: different Hamiltonian or parameters";
+        return FQ_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int W = dst->R.W;
+    Ctrl c;
+    int rc = read_ctrl(src, c, s);
+    if (rc) return rc;
+    if (c.error) { dst->err = "copy_state: source is in an error state"; return FQ_EINVAL; }
+    const i64 nmax = (i64)src->R.B * src->R.cap_t;
+    if (256 + (8 * W + 8) * (size_t)nmax > rec_bytes(W) * (size_t)dst->R.B * dst->R.cap_s) {
+        dst->err = "copy_state: destination slab too small to stage the source table";
+        return FQ_ECAPACITY;
+    }
+    char *buf = dst->inst.slab[1];
+    unsigned long long *cnt = (unsigned long long *)buf;
+    u64 *oa = (u64 *)(buf + 256);
+    double *ov = (double *)(oa + (size_t)W * nmax);
+    HIPCHK(dst, hipMemsetAsync(cnt, 0, 8, s));
+    const int grid = std::min(src->R.B, 4096);
+    if (W == 1) hipLaunchKernelGGL(k_pack<1>, dim3(grid), dim3(256), 0, s, (const Inst *)src->d_inst, oa, ov, cnt);
+    else hipLaunchKernelGGL(k_pack<2>, dim3(grid), dim3(256), 0, s, (const Inst *)src->d_inst, oa, ov, cnt);
+    HIPCHK(dst, hipGetLastError());
+    unsigned long long tot = 0;
+    HIPCHK(dst, hipMemcpyAsync(&tot, cnt, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(dst, hipStreamSynchronize(s));
+    if ((i64)tot > (i64)dst->R.B * dst->R.cap_t || tot == 0) {
+        dst->err = "copy_state: state does not fit the destination";
+        return FQ_ECAPACITY;
+    }
+    return load_state(dst, oa, ov, (i64)tot, c.shift, c.step, src->ref, src->yref, s);
+}
+
+int fq_autotune(fq_handle *src, const fq_layout *cand, int32_t n, int32_t trial_steps, void *scratch,
+                size_t scratch_bytes, double *ms, int32_t *best, void *stream)
+{
+    if (!src || !cand || n < 1 || trial_steps < 1 || !scratch || !ms || !best) return FQ_EINVAL;
+    *best = -1;
+    double tbest = 0.0;
+    for (int i = 0; i < n; i++) {
+        ms[i] = -1.0;
+        size_t need = 0;
+        fq_layout lo;
+        if (fq_workspace_size(&src->h, &src->p, &cand[i], &need, &lo) != FQ_OK || need > scratch_bytes) continue;
+        fq_handle *t = nullptr;
+        if (fq_create(&src->h, &src->p, &cand[i], scratch, scratch_bytes, &t) != FQ_OK) continue;
+        bool ok = fq_copy_state(t, src, stream) == FQ_OK && fq_run(t, 1, nullptr, stream) == FQ_OK;
+        if (ok) {
+            fq_set_timing(t, 1);
+            ok = fq_run(t, trial_steps, nullptr, stream) == FQ_OK;
+        }
+        if (ok) {
+            ms[i] = (t->time_ms[0] + t->time_ms[1] + t->time_ms[2]) / (double)t->launches;
+            if (*best < 0 || ms[i] < tbest) { *best = i; tbest = ms[i]; }
+        }
+        fq_destroy(t);
+    }
+    if (*best < 0) { src->err = "autotune: no candidate ran"; return FQ_EINVAL; }
+    return FQ_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ groups of instances
+
+namespace {
+
+// Host side of instances stepped together in one set of launches.
+struct Group {
+    std::vector<fq_handle *> h;  // in grid order
+    Exec X;
+    Ctrl *d_ctrl_out = nullptr;
+    std::vector<Ctrl> ctrl;
+};
+
+size_t group_header_bytes(i64 n, i64 buckets, i64 pblocks)
+{
+    return align256(sizeof(Inst *) * n) + align256(sizeof(u32) * buckets) + align256(sizeof(u32) * pblocks) +
+           align256(sizeof(Ctrl) * n);
+}
+
+i64 pmap_blocks(const Resolved &R) { return R.two_pass ? ((i64)1 << (R.log2G + R.log2SUB)) : 0; }
+
+// Builds the launch maps of `hs` in the device header `hdr`.  Instances are
+// placed in decreasing bucket count, so the first workgroup of every
+// instance with more than 64 buckets is a multiple of 64: the spawn
+// workgroups that append to one coarse sub-slab (bucket mod 64) then share
+// an XCD, and the second-pass map of every instance starts on XCD 0.
+int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &err)
+{
+    std::stable_sort(hs.begin(), hs.end(), [](const fq_handle *a, const fq_handle *b) { return a->R.B > b->R.B; });
+    const int n = (int)hs.size();
+    std::vector<const Inst *> ip(n);
+    std::vector<u32> map, pmap;
+    size_t lds_s = 0;
+    for (int i = 0; i < n; i++) {
+        ip[i] = hs[i]->d_inst;
+        for (int b = 0; b < hs[i]->R.B; b++) map.push_back(((u32)i << 14) | (u32)b);
+        append_pmap(hs[i]->R, (u32)i, pmap);
+        lds_s = std::max(lds_s, hs[i]->X.lds_s);
+    }
+    char *o = hdr;
+    const Inst **d_ip = (const Inst **)o;
+    o += align256(sizeof(Inst *) * n);
+    u32 *d_map = (u32 *)o;
+    o += align256(sizeof(u32) * map.size());
+    u32 *d_pmap = (u32 *)o;
+    o += align256(sizeof(u32) * pmap.size());
+    G.d_ctrl_out = (Ctrl *)o;
+    hipError_t e = hipMemcpy(d_ip, ip.data(), sizeof(Inst *) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_map, map.data(), sizeof(u32) * map.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pmap.empty())
+        e = hipMemcpy(d_pmap, pmap.data(), sizeof(u32) * pmap.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { err = std::string("group maps: ") + hipGetErrorString(e); return FQ_EHIP; }
+    G.h = hs;
+    G.X = hs[0]->X;
+    G.X.n = n;
+    G.X.insts = d_ip;
+    G.X.map = d_map;
+    G.X.grid = (int)map.size();
+    G.X.pmap = d_pmap;
+    G.X.pgrid = (int)pmap.size();
+    G.X.lds_s = lds_s;
+    G.ctrl.resize(n);
+    return FQ_OK;
+}
+
+// Runs `steps` steps of every instance of G (an instance that has failed or
+// reached its stop step does no work).  When rows is given, the statistics
+// rows of grid position j are appended at (*rows)[j] (advanced), if not
+// null.  Returns the status of the first failing instance (grid position in
+// *failed) after the chunk in which it failed.
+int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStream_t s, int *failed, std::string &err)
+{
+    const Exec &X = G.X;
+    i64 launched = 0;
+    int rc = FQ_OK;
+    while (launched < steps && rc == FQ_OK) {
+        const i64 chunk = std::min<i64>(RING, steps - launched);
+        hipLaunchKernelGGL(k_begin_chunk, dim3(1), dim3(256), 0, s, X.insts, X.n);
+        hipError_t e = hipGetLastError();
+        for (i64 k = 0; k < chunk && e == hipSuccess; k++) e = exec_step(X, s, nullptr);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_gather_ctrl, dim3(std::min(X.n, 1024)), dim3(64), 0, s, X.insts, X.n, G.d_ctrl_out);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(G.ctrl.data(), G.d_ctrl_out, sizeof(Ctrl) * X.n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { err = std::string("group step: ") + hipGetErrorString(e); return FQ_EHIP; }
+        for (int j = 0; j < X.n; j++) {
+            fq_handle *q = G.h[j];
+            const Ctrl &c = G.ctrl[j];
+            const i64 completed = c.step - q->step;
+            if (completed > 0 && rows && (*rows)[j]) {
+                e = hipMemcpy((*rows)[j], q->inst.ring, sizeof(StepStats) * completed, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) { err = std::string("group rows: ") + hipGetErrorString(e); return FQ_EHIP; }
+                (*rows)[j] += completed;
+            }
+            q->step = c.step;
+            q->parity = c.parity;
+            if (c.error && rc == FQ_OK) {
+                q->err = std::string(fqe_name(c.error)) + " at step " + std::to_string(c.step + 1) +
+                         (c.err_bucket >= 0 ? " (bucket " + std::to_string(c.err_bucket) + ")" : "");
+                err = q->err;
+                rc = fqe_status(c.error);
+                if (failed) *failed = j;
+            }
+        }
+        launched += chunk;
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch
+
+struct fq_batch {
+    std::vector<fq_handle *> inst;  // caller order
+    std::vector<int> pos;           // caller index -> grid position
+    Group G;
+    int failed = -1;
+    std::string err;
+};
+
+namespace {
+
+int batch_plan(int n, const fq_hamiltonian *h, const fq_params *p, const fq_layout *lay, std::vector<size_t> &off,
+               size_t &total, std::string &err)
+{
+    if (n < 1 || n > (1 << 17) || !h || !p || !lay) { err = "batch: need 1 <= n <= 131072 and arrays"; return FQ_EINVAL; }
+    i64 nb = 0, np = 0;
+    std::vector<size_t> sz(n);
+    Resolved R0;
+    for (int i = 0; i < n; i++) {
+        Resolved R;
+        fq_layout L;
+        int rc = resolve(&h[i], &p[i], &lay[i], R, L, err);
+        if (rc) { err = "batch instance " + std::to_string(i) + ": " + err; return rc; }
+        if (i == 0) R0 = R;
+        if (R.W != R0.W || variant(h[i].model, h[i].M) != variant(h[0].model, h[0].M) || R.block != R0.block ||
+            R.spawn_block != R0.spawn_block || R.slots != R0.slots) {
+            err = "batch instance " + std::to_string(i) +
+                  ": instances must share the model kind, addr_words, lds_slots, block and spawn_block";
+            return FQ_EINVAL;
+        }
+        sz[i] = align256(R.total);
+        nb += R.B;
+        np += pmap_blocks(R);
+    }
+    size_t o = group_header_bytes(n, nb, np);
+    off.resize(n);
+    for (int i = 0; i < n; i++) { off[i] = o; o += sz[i]; }
+    total = o;
+    return FQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fq_batch_workspace_size(int32_t n, const fq_hamiltonian *h, const fq_params *p, const fq_layout *lay,
+                            size_t *bytes)
+{
+    std::vector<size_t> off;
+    size_t total = 0;
+    int rc = batch_plan(n, h, p, lay, off, total, g_err);
+    if (rc) return rc;
+    if (bytes) *bytes = total;
+    return FQ_OK;
+}
+
+int fq_batch_create(int32_t n, const fq_hamiltonian *h, const fq_params *p, const fq_layout *lay, void *workspace,
+                    size_t bytes, fq_batch **out)
+{
+    if (!out) return FQ_EINVAL;
+    *out = nullptr;
+    std::vector<size_t> off;
+    size_t total = 0;
+    int rc = batch_plan(n, h, p, lay, off, total, g_err);
+    if (rc) return rc;
+    if (!workspace || ((uintptr_t)workspace & 255)) { g_err = "batch: workspace must be 256-byte aligned"; return FQ_EINVAL; }
+    if (bytes < total) { g_err = "batch: workspace too small"; return FQ_ENOMEM; }
+    fq_batch *b = new (std::nothrow) fq_batch();
+    if (!b) return FQ_ENOMEM;
+    char *ws = (char *)workspace;
+    for (int i = 0; i < n; i++) {
+        fq_handle *q = nullptr;
+        size_t sz = (i + 1 < n ? off[i + 1] : total) - off[i];
+        rc = fq_create(&h[i], &p[i], &lay[i], ws + off[i], sz, &q);
+        if (rc) {
+            g_err = "batch instance " + std::to_string(i) + ": " + g_err;
+            for (auto x : b->inst) fq_destroy(x);
+            delete b;
+            return rc;
+        }
+        b->inst.push_back(q);
+    }
+    rc = group_build(b->G, b->inst, ws, g_err);
+    if (rc) {
+        for (auto x : b->inst) fq_destroy(x);
+        delete b;
+        return rc;
+    }
+    b->pos.resize(n);
+    for (int j = 0; j < n; j++)
+        for (int i = 0; i < n; i++)
+            if (b->G.h[j] == b->inst[i]) b->pos[i] = j;
+    *out = b;
+    return FQ_OK;
+}
+
+int fq_batch_instance(fq_batch *b, int32_t i, fq_handle **out)
+{
+    if (!b || !out || i < 0 || i >= (int)b->inst.size()) return FQ_EINVAL;
+    *out = b->inst[i];
+    return FQ_OK;
+}
+
+int fq_batch_run(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *stream)
+{
+    if (!b || n_steps < 0) return FQ_EINVAL;
+    const int n = (int)b->inst.size();
+    for (int i = 0; i < n; i++)
+        if (!b->inst[i]->have_state) { b->err = "batch: instance " + std::to_string(i) + " has no state"; return FQ_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(256), 0, s, b->G.X.insts, n, (i64)n_steps);
+    std::vector<fq_step_stats *> rows(n, nullptr);
+    if (stats)
+        for (int i = 0; i < n; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
+    int failed = -1;
+    b->failed = -1;
+    int rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err);
+    if (failed >= 0)
+        for (int i = 0; i < n; i++)
+            if (b->pos[i] == failed) b->failed = i;
+    return rc;
+}
+
+int32_t fq_batch_failed(const fq_batch *b) { return b ? b->failed : -1; }
+
+int fq_batch_destroy(fq_batch *b)
+{
+    if (!b) return FQ_EINVAL;
+    for (auto q : b->inst) fq_destroy(q);
+    delete b;
+    return FQ_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ server
+
+namespace {
+
+struct Req {
+    fq_hamiltonian h;
+    fq_params p;
+    fq_layout L;
+    uint64_t start[2];
+    double start_val;
+    i64 n_steps;
+    size_t bytes = 0, off = 0;
+    fq_handle *q = nullptr;
+    fq_request_info info;
+    double sum_s = 0, sum_h = 0, sum_v = 0;
+};
+
+}  // namespace
+
+struct fq_server {
+    fq_server_config cfg;
+    char *hdr = nullptr, *arena = nullptr;
+    size_t arena_bytes = 0;
+    std::map<size_t, size_t> free_;  // arena offset -> bytes, coalesced
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> active;
+    std::unordered_map<uint64_t, Req> reqs;
+    uint64_t next_id = 1;
+    Group G;
+    bool dirty = true;
+    std::vector<fq_step_stats> rowbuf;
+    std::string err;
+
+    bool alloc(size_t bytes, size_t &off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+namespace {
+
+constexpr int SERVER_MAX_ACTIVE = 1024;
+
+size_t server_header_bytes(int max_active)
+{
+    return group_header_bytes(max_active, (i64)max_active * 16384, (i64)max_active * 4096);
+}
+
+void retire(fq_server *sv, Req &r)
+{
+    if (r.q) fq_destroy(r.q);
+    r.q = nullptr;
+    sv->release(r.off, r.bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+int fq_server_create(const fq_server_config *cfg, void *pool, size_t pool_bytes, fq_server **out)
+{
+    if (!out || !cfg) return FQ_EINVAL;
+    *out = nullptr;
+    if ((cfg->model != FQ_REAL1D && cfg->model != FQ_MOM1D) || (cfg->addr_words != 1 && cfg->addr_words != 2) ||
+        cfg->max_active < 1 || cfg->max_active > SERVER_MAX_ACTIVE || cfg->steps_per_tick < 1 ||
+        cfg->steps_per_tick > RING) {
+        g_err = "server: invalid configuration";
+        return FQ_EINVAL;
+    }
+    if (!pool || ((uintptr_t)pool & 255)) { g_err = "server: pool must be 256-byte aligned"; return FQ_EINVAL; }
+    const size_t hb = server_header_bytes(cfg->max_active);
+    if (pool_bytes < hb + 256) { g_err = "server: pool too small"; return FQ_ENOMEM; }
+    fq_server *sv = new (std::nothrow) fq_server();
+    if (!sv) return FQ_ENOMEM;
+    sv->cfg = *cfg;
+    sv->hdr = (char *)pool;
+    sv->arena = (char *)pool + hb;
+    sv->arena_bytes = (pool_bytes - hb) & ~(size_t)255;
+    sv->free_[0] = sv->arena_bytes;
+    *out = sv;
+    return FQ_OK;
+}
+
+const char *fq_server_last_error(const fq_server *sv) { return sv ? sv->err.c_str() : g_err.c_str(); }
+
+int fq_server_submit(fq_server *sv, const fq_hamiltonian *h, const fq_params *p, const fq_layout *layout,
+                     const uint64_t *start, double start_val, int64_t n_steps, uint64_t *id)
+{
+    if (!sv || !h || !p || !layout || !start || !id || n_steps < 1 || !std::isfinite(start_val) || start_val == 0.0)
+        return FQ_EINVAL;
+    if (h->model != sv->cfg.model || p->addr_words != sv->cfg.addr_words) {
+        sv->err = "submit: model or addr_words differ from the server's";
+        return FQ_EINVAL;
+    }
+    Req r;
+    r.h = *h;
+    r.p = *p;
+    r.L = *layout;
+    r.L.lds_slots = sv->cfg.lds_slots;
+    r.L.block = sv->cfg.block;
+    r.L.spawn_block = sv->cfg.spawn_block;
+    size_t bytes = 0;
+    fq_layout lo;
+    int rc = fq_workspace_size(&r.h, &r.p, &r.L, &bytes, &lo);
+    if (rc) { sv->err = "submit: " + g_err; return rc; }
+    if (h->model == FQ_MOM1D && h->M > 16) {
+        sv->err = "submit: a momentum-space server takes M <= 16";
+        return FQ_EINVAL;
+    }
+    r.bytes = align256(bytes);
+    if (r.bytes > sv->arena_bytes) { sv->err = "submit: the request can never fit the pool"; return FQ_EINVAL; }
+    r.start[0] = start[0];
+    r.start[1] = p->addr_words == 2 ? start[1] : 0;
+    r.start_val = start_val;
+    r.n_steps = n_steps;
+    memset(&r.info, 0, sizeof r.info);
+    r.info.state = FQ_REQ_QUEUED;
+    r.info.workspace_bytes = (int64_t)r.bytes;
+    const uint64_t rid = sv->next_id++;
+    sv->reqs.emplace(rid, r);
+    sv->queue.push_back(rid);
+    *id = rid;
+    return FQ_OK;
+}
+
+int fq_server_tick(fq_server *sv, void *stream, int32_t *n_active, int32_t *n_queued, int32_t *n_finished)
+{
+    if (!sv) return FQ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int finished = 0;
+    // admission in arrival order while memory and slots allow
+    while (!sv->queue.empty() && (int)sv->active.size() < sv->cfg.max_active) {
+        const uint64_t rid = sv->queue.front();
+        Req &r = sv->reqs[rid];
+        if (!sv->alloc(r.bytes, r.off)) break;
+        sv->queue.pop_front();
+        int rc = fq_create(&r.h, &r.p, &r.L, sv->arena + r.off, r.bytes, &r.q);
+        if (rc == FQ_OK) rc = fq_set_state(r.q, r.start, &r.start_val, 1, 0.0, 0, r.start, r.start_val, stream);
+        if (rc == FQ_OK) {
+            hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, &r.q->d_ctrl->stop_step, (i64)r.n_steps);
+            if (hipGetLastError() != hipSuccess) rc = FQ_EHIP;
+        }
+        if (rc != FQ_OK) {
+            r.info.state = FQ_REQ_FAILED;
+            r.info.status = rc;
+            retire(sv, r);
+            finished++;
+            continue;
+        }
+        r.info.state = FQ_REQ_RUNNING;
+        sv->active.push_back(rid);
+        sv->dirty = true;
+    }
+    if (!sv->active.empty()) {
+        if (sv->dirty) {
+            std::vector<fq_handle *> hs;
+            for (auto rid : sv->active) hs.push_back(sv->reqs[rid].q);
+            int rc = group_build(sv->G, hs, sv->hdr, sv->err);
+            if (rc) return rc;
+            sv->dirty = false;
+        }
+        const int n = (int)sv->G.h.size();
+        const i64 T = sv->cfg.steps_per_tick;
+        sv->rowbuf.resize((size_t)n * T);
+        std::vector<fq_step_stats *> rows(n);
+        for (int j = 0; j < n; j++) rows[j] = sv->rowbuf.data() + (size_t)j * T;
+        int failed = -1;
+        std::string err;
+        int rc = group_steps(sv->G, T, &rows, s, &failed, err);
+        if (rc == FQ_EHIP) { sv->err = err; return rc; }
+        // account the rows and retire finished or failed solves
+        std::unordered_map<const fq_handle *, int> posof;
+        for (int j = 0; j < n; j++) posof[sv->G.h[j]] = j;
+        std::vector<uint64_t> keep;
+        for (auto rid : sv->active) {
+            Req &r = sv->reqs[rid];
+            const int j = posof[r.q];
+            const fq_step_stats *b0 = sv->rowbuf.data() + (size_t)j * T;
+            for (const fq_step_stats *x = b0; x < rows[j]; x++) {
+                r.info.last = *x;
+                if (2 * x->step > r.n_steps) {
+                    r.sum_s += x->shift;
+                    r.sum_h += x->hproj;
+                    r.sum_v += x->vproj;
+                    r.info.n_mean++;
+                }
+            }
+            r.info.steps_done = r.q->step;
+            const Ctrl &c = sv->G.ctrl[j];
+            if (c.error) {
+                r.info.state = FQ_REQ_FAILED;
+                r.info.status = fqe_status(c.error);
+            } else if (r.q->step >= r.n_steps) {
+                r.info.state = FQ_REQ_DONE;
+            }
+            if (r.info.n_mean > 0) {
+                r.info.mean_shift = r.sum_s / (double)r.info.n_mean;
+                r.info.mean_hproj = r.sum_h / (double)r.info.n_mean;
+                r.info.mean_vproj = r.sum_v / (double)r.info.n_mean;
+            }
+            if (r.info.state == FQ_REQ_RUNNING) {
+                keep.push_back(rid);
+            } else {
+                retire(sv, r);
+                finished++;
+                sv->dirty = true;
+            }
+        }
+        sv->active.swap(keep);
+    }
+    if (n_active) *n_active = (int32_t)sv->active.size();
+    if (n_queued) *n_queued = (int32_t)sv->queue.size();
+    if (n_finished) *n_finished = finished;
+    return FQ_OK;
+}
+
+int fq_server_poll(fq_server *sv, uint64_t id, fq_request_info *info)
+{
+    if (!sv || !info) return FQ_EINVAL;
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return FQ_ENOTFOUND;
+    *info = it->second.info;
+    return FQ_OK;
+}
+
+int fq_server_destroy(fq_server *sv)
+{
+    if (!sv) return FQ_EINVAL;
+    for (auto &kv : sv->reqs)
+        if (kv.second.q) fq_destroy(kv.second.q);
+    delete sv;
     return FQ_OK;
 }
 

@@ -112,6 +112,15 @@ __device__ __forceinline__ void set_error(Ctrl *c, int code, int bucket)
     if (atomicCAS(&c->error, 0, code) == 0) c->err_bucket = bucket;
 }
 
+// an instance does no work once it has failed or has reached its stop step
+// (instances of a batch stop independently; all kernels of one step see the
+// same step number, which only the finalize kernel advances)
+__device__ __forceinline__ int halted(Ctrl *c)
+{
+    const int e = __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return e != 0 || c->step >= c->stop_step;
+}
+
 template <int W> struct Rec;
 template <> struct Rec<1> {
     u64 a;
@@ -285,19 +294,19 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
 // from an LDS counter, one thread per group reserves a contiguous run with
 // one global atomic, then the records are stored into the runs.  With the
 // two-pass partition a group is a coarse group of buckets and the run lies in
-// the coarse sub-slab of this workgroup (blockIdx mod 64); otherwise a group
+// the coarse sub-slab of the producing bucket (bucket mod 64); otherwise a group
 // is a bucket and the run lies in its slab.
 template <int W> struct SpawnOut {
     typedef typename AddrOf<W>::T T;
     const Inst &I;
     const Lds &L;
     int out_par, G, gshift, sub;
-    __device__ SpawnOut(const Inst &I_, const Lds &L_, int out_par_) : I(I_), L(L_), out_par(out_par_)
+    __device__ SpawnOut(const Inst &I_, const Lds &L_, int out_par_, int b) : I(I_), L(L_), out_par(out_par_)
     {
         const int log2G = I.two_pass ? I.log2G : I.log2B;
         G = 1 << log2G;
         gshift = I.log2B - log2G;
-        sub = (int)(blockIdx.x & ((1u << I.log2SUB) - 1));
+        sub = b & ((1 << I.log2SUB) - 1);
     }
     __device__ int *gcnt() const { return (int *)(L.misc + 64); }  // G <= 64 counters
     __device__ i64 *gbase() const { return L.misc + 96; }          // G <= 64 run bases
@@ -357,7 +366,7 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
     typedef typename AddrOf<W>::T T;
     constexpr int MAXM = MODEL == 1 ? 16 : 32;
     const int tid = threadIdx.x;
-    const SpawnOut<W> out(I, L, par);
+    const SpawnOut<W> out(I, L, par, b);
     const double dtau = I.dtau;
     const i64 nu = u_hi;
     if (nu <= 0) return;
@@ -467,7 +476,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
 {
     typedef typename AddrOf<W>::T T;
     const int tid = threadIdx.x;
-    const SpawnOut<W> out(I, L, par);
+    const SpawnOut<W> out(I, L, par, b);
     int top = 1;
     while (2 * top <= nS) top *= 2;
     for (i64 base = 0; base < A; base += BS) {
@@ -534,7 +543,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     const int slots = I.slots;
     __shared__ int s_err;
 
-    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) s_err = halted(ctrl);
     __syncthreads();
     if (s_err) return;
 
@@ -763,7 +772,7 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
     const int tid = threadIdx.x;
     Ctrl *ctrl = I.ctrl;
     __shared__ int s_err;
-    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) s_err = halted(ctrl);
     __syncthreads();
     if (s_err) return;
     const i64 n = ctrl->step;
@@ -867,7 +876,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
     __shared__ i64 base[256];
     Ctrl *ctrl = I.ctrl;
     const int tid = threadIdx.x;
-    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) s_err = halted(ctrl);
     __syncthreads();
     if (s_err) return;
     const int q = ctrl->spawn_par;
@@ -925,7 +934,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
     __shared__ int s_err;
     Ctrl *ctrl = I.ctrl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) s_err = __hip_atomic_load(&ctrl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) s_err = halted(ctrl);
     __syncthreads();
     if (s_err) return;
     const i64 n = ctrl->step;
