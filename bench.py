@@ -92,6 +92,124 @@ def cpu_baseline(state, cfg, step_index, shift, budget_s=15.0):
                 entries_per_s=k / dt)
 
 
+def _spec(inst, **lay):
+    """Solver keyword arguments of a synthetic instance description."""
+    import math
+    M, N, tgt = inst["M"], inst["N"], inst["target"]
+    dim = math.comb(N + M - 1, N)
+    table = int(min(dim, 1.2 * tgt)) + 4096
+    spawn = int(2.5 * tgt) + 65536
+    return dict(model=inst["model"], M=M, N=N, t=inst["t"], u=inst["u"], dtau=inst["dtau"],
+                target_walkers=tgt, seed=inst["seed"], addr_words=inst["W"],
+                threshold=inst["theta"], table_capacity=table, spawn_capacity=spawn, **lay)
+
+
+BATCH_LAYOUT = dict(lds_slots=2048, block=512, spawn_block=256)
+
+
+def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
+    """The 64-instance batch (real-space, M = N in 8..24, u log-uniform in
+    [1, 10], N_t 1e4..1e7): walker-steps/s of the batch against the same
+    instances stepped one at a time (plain per-instance launches), from the
+    same state; the two runs must agree bit for bit."""
+    specs = [_spec(x, **BATCH_LAYOUT) for x in synthetic.batch_instances(n)]
+    b = fq.Batch(specs)
+    for i, sp in enumerate(specs):
+        a = fq.start_address(sp["model"], sp["M"], sp["N"])
+        b.instance(i).set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup:
+        k = min(500, warmup - done)
+        b.run(k)
+        done += k
+        log(f"[bench] batch warmup {done}/{warmup} ({time.perf_counter() - t0:.1f} s)")
+    plain = []
+    for i, sp in enumerate(specs):
+        s = fq.Solver(**sp)
+        s.copy_state_from(b.instance(i))
+        plain.append(s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = b.run(steps)
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t1
+    wall_p = 0.0
+    same = True
+    for i, s in enumerate(plain):
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        si = s.run(steps)
+        torch.cuda.synchronize()
+        wall_p += time.perf_counter() - t2
+        same &= si.tobytes() == st[i].tobytes()
+        s.close()
+    b.close()
+    ws = float(st["norm"].sum())
+    out = dict(workload=f"batch of {n} real-space 1D Bose-Hubbard instances (M = N in 8..24, "
+                        f"u log-uniform in [1, 10], N_t 1e4..1e7)",
+               instances=n, warmup=warmup, steps=steps, walkers_total=float(st["norm"][:, -1].sum()),
+               walker_steps_per_s=ws / wall_b, ms_per_step=wall_b / steps * 1e3,
+               plain_walker_steps_per_s=ws / wall_p, plain_ms_per_step=wall_p / steps * 1e3,
+               speedup_vs_plain=wall_p / wall_b, identical_to_plain=bool(same))
+    log(f"[bench] batched {out['walker_steps_per_s']:.4g} walker-steps/s, plain "
+        f"{out['plain_walker_steps_per_s']:.4g} ({out['speedup_vs_plain']:.2f}x), identical {same}")
+    return out
+
+
+def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
+    """The first n_req requests of the Poisson stream (lambda = 50/s, M = N in
+    6..20, u in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7]) served
+    with continuous batching under an HBM budget; latency = completion -
+    arrival."""
+    reqs = synthetic.poisson_requests(1000)[:n_req]
+    free = torch.cuda.mem_get_info()[0]
+    pool = int(min(budget, 0.85 * free))
+    sv = fq.Server(fq.REAL1D, pool, lds_slots=BATCH_LAYOUT["lds_slots"], block=BATCH_LAYOUT["block"],
+                   spawn_block=BATCH_LAYOUT["spawn_block"], max_active=max_active,
+                   steps_per_tick=tick)
+    ids, comp = [], {}
+    t0 = time.perf_counter()
+    i = 0
+    ticks = 0
+    while len(comp) < n_req:
+        now = time.perf_counter() - t0
+        while i < n_req and reqs[i]["arrival"] - reqs[0]["arrival"] <= now:
+            r = reqs[i]
+            sp = _spec(r)
+            sp.pop("addr_words")
+            ids.append(sv.submit(sp, fq.start_address(r["model"], r["M"], r["N"]), 10.0, r["steps"]))
+            i += 1
+        active, queued, fin = sv.tick()
+        ticks += 1
+        now = time.perf_counter() - t0
+        for k, rid in enumerate(ids):
+            if rid not in comp and sv.poll(rid)["state"] >= fq.REQ_DONE:
+                comp[rid] = now
+        if active == 0 and queued == 0 and i < n_req:
+            time.sleep(max(0.0, reqs[i]["arrival"] - reqs[0]["arrival"] - now))
+        if ticks % 20 == 0:
+            log(f"[bench] served: {len(comp)}/{n_req} done, {active} active, {queued} queued "
+                f"({now:.1f} s)")
+    lat, ws, ok = [], 0.0, True
+    for k, rid in enumerate(ids):
+        info = sv.poll(rid)
+        ok &= info["state"] == fq.REQ_DONE
+        lat.append(comp[rid] - (reqs[k]["arrival"] - reqs[0]["arrival"]))
+        ws += info["walker_steps"]
+    makespan = max(comp.values())
+    sv.close()
+    out = dict(workload=f"first {n_req} requests of a Poisson stream (lambda = 50/s; real-space "
+                        "M = N in 6..20, u in [1, 10], 2e3..2e4 steps, N_t log-uniform in "
+                        "[1e3, 1e7]), continuous batching",
+               requests=n_req, pool_bytes=pool, steps_per_tick=tick, ticks=ticks,
+               p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+               walker_steps_per_s=ws / makespan, makespan_s=makespan, all_done=bool(ok))
+    log(f"[bench] served p50 {out['p50_latency_s']:.2f} s p99 {out['p99_latency_s']:.2f} s, "
+        f"{out['walker_steps_per_s']:.4g} walker-steps/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +223,11 @@ def main():
     ap.add_argument("--slots", type=int, default=None)
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--spawn-block", type=int, default=None)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served measurement")
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--batch-warmup", type=int, default=1500)
+    ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a streaming negation over this many MiB (reads and writes "
                          "that many bytes): the reference kernel for HBM byte counters")
@@ -189,7 +312,11 @@ def main():
     for k, b in per_kernel.items():
         t_s = kms[k] / 1e3 / max(nl, 1)
         kern[k] = {"mean_ms": t_s * 1e3, "algorithmic_bytes": b, "achieved_GBs": b / t_s / 1e9}
-    kern["partition"] = {"mean_ms": kms["partition"] / max(nl, 1)}
+    kern["partition"] = {"mean_ms": kms["partition"] / max(nl, 1),
+                         "algorithmic_bytes": float(2 * rec * nxt.mean())}
+    kern["partition"]["achieved_GBs"] = (kern["partition"]["algorithmic_bytes"] /
+                                         max(kern["partition"]["mean_ms"], 1e-9) / 1e6)
+    kern["finalize"] = {"mean_ms": kms["finalize"] / max(nl, 1)}
     dom = max(per_kernel, key=lambda k: kern[k]["mean_ms"])
     achieved = kern[dom]["achieved_GBs"]
     out = {
@@ -223,11 +350,18 @@ def main():
         "spawns_per_s": float(st["spawns"].sum()) / wall,
         "shift_mean": float(st["shift"].mean()),
     }
-    if not args.no_cpu_baseline:
-        addrs, vals, shift, step = s.get_state()
-        s.close()
-        del s
+    state = s.get_state() if not args.no_cpu_baseline else None
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = bench_batched(fq, torch, warmup=args.batch_warmup, steps=args.batch_steps)
         torch.cuda.empty_cache()
+    if not args.no_serve:
+        out["served"] = bench_served(fq, torch, n_req=args.serve_requests)
+        torch.cuda.empty_cache()
+    if state is not None:
+        addrs, vals, shift, step = state
         log(f"[bench] cpu baseline on {len(vals)} entries (budget {args.cpu_budget} s)")
         out["cpu_baseline"] = cpu_baseline((addrs, vals), cfg, step + 1, shift, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -158,12 +158,12 @@ int fq_read_merged_dump(fq_handle *q, uint64_t *addr, double *value, int64_t cap
                         void *stream);
 
 /* Kernel timing with HIP events recorded on the run stream around the
- * launches of each step while `enable` is non-zero (four events per step).
+ * launches of each step while `enable` is non-zero (five events per step).
  * fq_kernel_time fills ms[0..n-1] with the summed milliseconds since the
  * last reset of: [0] the merge kernel (annihilation, compression, projected
- * energy, compaction), [1] the spawn kernel, [2] the spawn partition and the
- * shift update; entries beyond [2] are zero.  *steps receives the number of
- * timed steps. */
+ * energy, compaction), [1] the spawn kernel, [2] the second pass of the
+ * spawn partition, [3] the reduction and shift update; entries beyond [3]
+ * are zero.  *steps receives the number of timed steps. */
 int fq_set_timing(fq_handle *q, int32_t enable);
 int fq_kernel_time(fq_handle *q, double *ms, int32_t n, int64_t *steps, int32_t reset);
 
@@ -272,6 +272,7 @@ typedef struct {
     double mean_shift, mean_hproj, mean_vproj;  /* over steps > n_steps / 2 */
     int64_t n_mean;
     int64_t workspace_bytes;
+    double walker_steps;        /* sum of ||c||_1 over the completed steps  */
 } fq_request_info;
 
 int fq_server_create(const fq_server_config *cfg, void *pool, size_t pool_bytes, fq_server **out);

@@ -64,7 +64,8 @@ class ServerConfig(C.Structure):
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int64),
                 ("last", StepStats), ("mean_shift", C.c_double), ("mean_hproj", C.c_double),
-                ("mean_vproj", C.c_double), ("n_mean", C.c_int64), ("workspace_bytes", C.c_int64)]
+                ("mean_vproj", C.c_double), ("n_mean", C.c_int64), ("workspace_bytes", C.c_int64),
+                ("walker_steps", C.c_double)]
 
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
@@ -307,13 +308,14 @@ class Solver:
 
     def kernel_time(self, reset=False):
         """Summed HIP-event milliseconds of the timed steps as a dict with keys
-        merge, spawn, partition (spawn partition + shift update), and the
-        number of timed steps."""
-        ms = np.zeros(3)
+        merge, spawn, partition (second pass), finalize (reduction and shift
+        update), and the number of timed steps."""
+        ms = np.zeros(4)
         n = C.c_int64(0)
-        self._check(lib().fq_kernel_time(self.h, _p(ms, C.c_double), 3, C.byref(n), 1 if reset else 0),
+        self._check(lib().fq_kernel_time(self.h, _p(ms, C.c_double), 4, C.byref(n), 1 if reset else 0),
                     "fq_kernel_time")
-        return dict(merge=float(ms[0]), spawn=float(ms[1]), partition=float(ms[2])), n.value
+        return dict(merge=float(ms[0]), spawn=float(ms[1]), partition=float(ms[2]),
+                    finalize=float(ms[3])), n.value
 
     def debug_counters(self, reset=False):
         out = np.zeros(13)
@@ -505,7 +507,7 @@ class Server:
         return dict(state=info.state, status=info.status, steps_done=info.steps_done, last=last,
                     mean_shift=info.mean_shift, mean_hproj=info.mean_hproj,
                     mean_vproj=info.mean_vproj, n_mean=info.n_mean,
-                    workspace_bytes=info.workspace_bytes)
+                    workspace_bytes=info.workspace_bytes, walker_steps=info.walker_steps)
 
     def close(self):
         if getattr(self, "sv", None):

@@ -38,6 +38,8 @@ __device__ __forceinline__ U128 operator~(U128 a) { return {~a.lo, ~a.hi}; }
 __device__ __forceinline__ bool operator==(U128 a, U128 b) { return a.lo == b.lo && a.hi == b.hi; }
 __device__ __forceinline__ bool operator!=(U128 a, U128 b) { return !(a == b); }
 
+__device__ __forceinline__ u32 shl(u32 x, int s) { return s >= 32 ? 0u : x << s; }
+__device__ __forceinline__ u32 shr(u32 x, int s) { return s >= 32 ? 0u : x >> s; }
 __device__ __forceinline__ u64 shl(u64 x, int s) { return s >= 64 ? 0ull : x << s; }
 __device__ __forceinline__ u64 shr(u64 x, int s) { return s >= 64 ? 0ull : x >> s; }
 __device__ __forceinline__ U128 shl(U128 x, int s)
@@ -54,15 +56,18 @@ __device__ __forceinline__ U128 shr(U128 x, int s)
     if (s >= 64) return {x.hi >> (s - 64), 0};
     return {(x.lo >> s) | (x.hi << (64 - s)), x.hi >> s};
 }
+__device__ __forceinline__ int popc(u32 x) { return __popc(x); }
 __device__ __forceinline__ int popc(u64 x) { return __popcll(x); }
 __device__ __forceinline__ int popc(U128 x) { return __popcll(x.lo) + __popcll(x.hi); }
 // trailing zeros of a non-zero value
+__device__ __forceinline__ int ctz(u32 x) { return __ffs((int)x) - 1; }
 __device__ __forceinline__ int ctz(u64 x) { return __ffsll((long long)x) - 1; }
 __device__ __forceinline__ int ctz(U128 x) { return x.lo ? ctz(x.lo) : 64 + ctz(x.hi); }
 // index of the highest set bit of a non-zero value
 __device__ __forceinline__ int msb(u64 x) { return 63 - __clzll((long long)x); }
 __device__ __forceinline__ int msb(U128 x) { return x.hi ? 64 + msb(x.hi) : msb(x.lo); }
 template <class T> __device__ __forceinline__ T one_at(int p);
+template <> __device__ __forceinline__ u32 one_at<u32>(int p) { return 1u << p; }
 template <> __device__ __forceinline__ u64 one_at<u64>(int p) { return 1ull << p; }
 template <> __device__ __forceinline__ U128 one_at<U128>(int p)
 {
@@ -70,6 +75,7 @@ template <> __device__ __forceinline__ U128 one_at<U128>(int p)
 }
 // bits [0, p)
 template <class T> __device__ __forceinline__ T mask_below(int p);
+template <> __device__ __forceinline__ u32 mask_below<u32>(int p) { return p >= 32 ? ~0u : (1u << p) - 1; }
 template <> __device__ __forceinline__ u64 mask_below<u64>(int p) { return p >= 64 ? ~0ull : (1ull << p) - 1; }
 template <> __device__ __forceinline__ U128 mask_below<U128>(int p)
 {
@@ -77,6 +83,7 @@ template <> __device__ __forceinline__ U128 mask_below<U128>(int p)
     if (p >= 64) return {~0ull, p == 64 ? 0ull : (1ull << (p - 64)) - 1};
     return {(1ull << p) - 1, 0};
 }
+__device__ __forceinline__ bool is_zero(u32 x) { return x == 0; }
 __device__ __forceinline__ bool is_zero(u64 x) { return x == 0; }
 __device__ __forceinline__ bool is_zero(U128 x) { return (x.lo | x.hi) == 0; }
 
@@ -103,6 +110,41 @@ __device__ __forceinline__ int select(U128 x, int j)
 {
     int c = __popcll(x.lo);
     return j < c ? select64(x.lo, j) : 64 + select64(x.hi, j - c);
+}
+
+// Select with a byte table: lut[8 v + r] is the position of the r-th set bit
+// of the byte v.  Byte-wise popcounts (SWAR) and their prefix sums locate
+// the byte that holds the j-th set bit without a search.
+__device__ __forceinline__ int select_lut(u32 w, int j, const unsigned char *lut)
+{
+    u32 c = w - ((w >> 1) & 0x55555555u);
+    c = (c & 0x33333333u) + ((c >> 2) & 0x33333333u);
+    c = (c + (c >> 4)) & 0x0f0f0f0fu;                       // set bits per byte
+    const u32 pre = c * 0x01010101u;                        // byte k: bits in bytes 0..k
+    const u32 ge = ((pre | 0x80808080u) - (u32)(j + 1) * 0x01010101u) & 0x80808080u;
+    const int b = 4 - __popc(ge);                           // bytes with prefix <= j
+    const int before = b == 0 ? 0 : (int)((pre << (32 - 8 * b)) >> 24);
+    return 8 * b + lut[((w >> (8 * b)) & 0xffu) * 8 + (u32)(j - before)];
+}
+__device__ __forceinline__ int select_lut(u64 x, int j, const unsigned char *lut)
+{
+    const u32 lo = (u32)x;
+    const int c = __popc(lo);
+    const bool up = j >= c;
+    return (up ? 32 : 0) + select_lut(up ? (u32)(x >> 32) : lo, up ? j - c : j, lut);
+}
+__device__ __forceinline__ int select_lut(U128 x, int j, const unsigned char *lut)
+{
+    const int c = __popcll(x.lo);
+    const bool up = j >= c;
+    return (up ? 64 : 0) + select_lut(up ? x.hi : x.lo, up ? j - c : j, lut);
+}
+// table of select_lut, 2048 bytes
+__device__ __forceinline__ unsigned char select_lut_entry(int i)
+{
+    u32 v = (u32)i >> 3, r = (u32)i & 7;
+    for (u32 k = 0; k < r && v; k++) v &= v - 1;  // drop the r lowest set bits
+    return v ? (unsigned char)(__ffs((int)v) - 1) : (unsigned char)0;
 }
 
 // address word access
@@ -148,10 +190,10 @@ __device__ __forceinline__ R4 philox4x32_10(u32 c0, u32 c1, u32 c2, u32 c3, u32 
 {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
-        u32 hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        u32 hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        u32 y0 = hi1 ^ c1 ^ k0, y2 = hi0 ^ c3 ^ k1;
-        c0 = y0; c1 = lo1; c2 = y2; c3 = lo0;
+        // one 32x32 -> 64 product gives both halves (v_mad_u64_u32)
+        const u64 p0 = (u64)0xD2511F53u * c0, p1 = (u64)0xCD9E8D57u * c2;
+        const u32 y0 = (u32)(p1 >> 32) ^ c1 ^ k0, y2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        c0 = y0; c1 = (u32)p1; c2 = y2; c3 = (u32)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

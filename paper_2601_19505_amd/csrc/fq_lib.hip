@@ -75,10 +75,19 @@ __global__ __launch_bounds__(1024) void k_finalize(const Inst *const *insts)
 // runs that different workgroups append to one bucket's slab then meet in
 // that XCD's L2, which merges partial cache lines before they are written
 // back.
-template <int W> __global__ __launch_bounds__(1024) void k_part(const Inst *const *insts, const u32 *map)
+#ifndef FQ_PART_BS
+#define FQ_PART_BS 1024
+#endif
+#ifndef FQ_PART_RPT
+#define FQ_PART_RPT 8
+#endif
+constexpr int PART_BS = FQ_PART_BS;    // threads per workgroup of the second pass
+constexpr int PART_RPT = FQ_PART_RPT;  // records per thread and round
+
+template <int W> __global__ __launch_bounds__(PART_BS) void k_part(const Inst *const *insts, const u32 *map)
 {
     const u32 m = map[blockIdx.x];
-    partition_coarse<W, 1024, 8>(*insts[m >> 14], (int)(m & 0x3fffu));
+    partition_coarse<W, PART_BS, PART_RPT>(*insts[m >> 14], (int)(m & 0x3fffu));
 }
 
 // start of a chunk of steps: statistics rows are stored from row 0
@@ -224,7 +233,7 @@ __global__ void k_set_i64(i64 *p, i64 v) { *p = v; }
 namespace {
 
 constexpr i64 RING = 4096;
-constexpr int NEV = 4;  // timing events per step: merge | spawn | partition + finalize
+constexpr int NEV = 5;  // timing events per step: merge | spawn | partition | finalize
 constexpr int REFCAP = 1 << 15;
 
 template <int W, int MODEL>
@@ -269,8 +278,8 @@ size_t lds_bytes(int W, int slots)
 }
 
 // spawn kernel: three 32-bit words per table entry (unit offset, count word,
-// permutation) and the scratch words
-size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8; }
+// permutation), the scratch words and the 2048-byte select table
+size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048; }
 
 constexpr size_t LDS_MAX = 160 * 1024;
 static_assert(sizeof(Ctrl) % 4 == 0, "Ctrl is copied in 32-bit words");
@@ -441,22 +450,23 @@ void append_pmap(const Resolved &R, u32 inst, std::vector<u32> &out)
     }
 }
 
-hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s)
+hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s, hipEvent_t mid = nullptr)
 {
     const void *kf = step_kernel(X.W, X.var, X.spawn_block, true);
     void *args[] = {(void *)&X.insts, (void *)&X.map, (void *)&mode};
     hipError_t e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.spawn_block), args, X.lds_s, s);
+    if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e == hipSuccess && X.pgrid > 0) {
-        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(1024), 0, s, X.insts, X.pmap);
-        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(1024), 0, s, X.insts, X.pmap);
+        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(PART_BS), 0, s, X.insts, X.pmap);
+        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(PART_BS), 0, s, X.insts, X.pmap);
         e = hipGetLastError();
     }
     return e;
 }
 
-// one step of every instance of X: merge, spawn (+ partition), finalize;
-// with `ev`, events before the merge, after the merge, after the spawn and
-// partition, and after the finalize
+// one step of every instance of X: merge, spawn, second partition pass,
+// finalize; with `ev`, NEV events: before the merge and after each of the
+// four kernels
 hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev)
 {
     hipError_t e = hipSuccess;
@@ -467,13 +477,13 @@ hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev)
         e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.block), args, X.lds_m, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
-    if (e == hipSuccess) e = launch_spawn(X, 0, s);
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[2], s);
+    if (e == hipSuccess) e = launch_spawn(X, 0, s, ev ? ev[2] : nullptr);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finalize, dim3(X.n), dim3(1024), 0, s, X.insts);
         e = hipGetLastError();
     }
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[4], s);
     return e;
 }
 
@@ -496,7 +506,7 @@ struct fq_handle {
     int parity;
     std::string err;
     int timing;
-    double time_ms[3];
+    double time_ms[NEV - 1];
     i64 launches;
     std::vector<hipEvent_t> ev;
     std::vector<StepStats> ring_host;
@@ -1099,7 +1109,7 @@ int fq_autotune(fq_handle *src, const fq_layout *cand, int32_t n, int32_t trial_
             ok = fq_run(t, trial_steps, nullptr, stream) == FQ_OK;
         }
         if (ok) {
-            ms[i] = (t->time_ms[0] + t->time_ms[1] + t->time_ms[2]) / (double)t->launches;
+            ms[i] = (t->time_ms[0] + t->time_ms[1] + t->time_ms[2] + t->time_ms[3]) / (double)t->launches;
             if (*best < 0 || ms[i] < tbest) { *best = i; tbest = ms[i]; }
         }
         fq_destroy(t);
@@ -1563,6 +1573,7 @@ int fq_server_tick(fq_server *sv, void *stream, int32_t *n_active, int32_t *n_qu
             const fq_step_stats *b0 = sv->rowbuf.data() + (size_t)j * T;
             for (const fq_step_stats *x = b0; x < rows[j]; x++) {
                 r.info.last = *x;
+                r.info.walker_steps += x->norm;
                 if (2 * x->step > r.n_steps) {
                     r.sum_s += x->shift;
                     r.sum_h += x->hproj;

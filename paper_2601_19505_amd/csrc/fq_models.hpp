@@ -216,7 +216,8 @@ __device__ __forceinline__ T mom_move(const ModelConst &C, const MomP<T> &P, int
 // inverse generation probability.  No data-dependent branches, so the lanes
 // of a wave stay converged.
 template <class T>
-__device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u32 w1, double &h, i64 &qnum)
+__device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u32 w1, double &h, i64 &qnum,
+                                            const unsigned char *lut)
 {
     const int M = C.M;
     const T st = run_starts(a);
@@ -230,13 +231,13 @@ __device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u3
     const int t = diag ? 0 : pi - D;
     // j = largest integer with j (j - 1) / 2 <= t; the float root is exact to
     // within one and corrected
-    int j = (int)((1.0f + __fsqrt_rn(1.0f + 8.0f * (float)t)) * 0.5f);
+    int j = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
     j -= (j * (j - 1) / 2 > t) ? 1 : 0;
     j += ((j + 1) * j / 2 <= t) ? 1 : 0;
     const int i = t - j * (j - 1) / 2;
     const T x = diag ? dpos : st;
-    const int sp = select(x, diag ? pi : i);
-    const int sq = select(x, diag ? pi : j);
+    const int sp = select_lut(x, diag ? pi : i, lut);
+    const int sq = select_lut(x, diag ? pi : j, lut);
     const int p = sp - popc(a & mask_below<T>(sp));
     const int q = sq - popc(a & mask_below<T>(sq));
     const int K = mod_add(p, q, M);
@@ -248,8 +249,8 @@ __device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u3
     const int r = idx <= half ? idx : K + 1 + (idx - half - 1);
     int s = K - r;
     if (s < 0) s += M;
-    const int sr = r == 0 ? 0 : select(z, r - 1) + 1;
-    const int ss = s == 0 ? 0 : select(z, s - 1) + 1;
+    const int sr = r == 0 ? 0 : select_lut(z, r - 1, lut) + 1;
+    const int ss = s == 0 ? 0 : select_lut(z, s - 1, lut) + 1;
     const int np = runlen(a, sp), nq = runlen(a, sq), nr = runlen(a, sr), ns = runlen(a, ss);
     const int A = np * (nq - (p == q ? 1 : 0));
     const int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));

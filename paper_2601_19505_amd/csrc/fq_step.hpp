@@ -466,64 +466,90 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
 // Stochastic spawns (Sec. 3.2, matrix compression): ceil|c| attempts per
 // parent, each an independent draw.  The A attempts of the nS stochastic
 // entries (permuted indices w0_ .. w0_+nS-1, attempt offsets in info[2 w])
-// are enumerated flat: in each round thread t takes attempt base + t, finds
-// its parent by a binary search with a fixed number of steps and generates
-// one record with branch-free code, so all lanes of a wave do the same work.
+// are enumerated flat: in each round thread t takes attempts
+// base + r BS + t (r < NR), finds each attempt's parent by a binary search
+// with a fixed number of steps and generates the record with branch-free
+// code, so all lanes of a wave do the same work.  NR records per thread and
+// round make the runs appended to each destination group longer.
+#ifndef FQ_SPAWN_NR
+#define FQ_SPAWN_NR 4
+#endif
 template <int W, int MODEL, int BS>
 __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const int b, const int par,
                                            const u32 spawn_step, const int w0_, const int nS, const u32 *info,
-                                           const u32 *perm, const i64 A)
+                                           const u32 *perm, const i64 A, const unsigned char *lut)
 {
     typedef typename AddrOf<W>::T T;
+    constexpr int NR = FQ_SPAWN_NR;
     const int tid = threadIdx.x;
     const SpawnOut<W> out(I, L, par, b);
+    const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
     int top = 1;
     while (2 * top <= nS) top *= 2;
-    for (i64 base = 0; base < A; base += BS) {
+    for (i64 base = 0; base < A; base += (i64)NR * BS) {
         out.begin();
-        const i64 kf = base + tid;
-        const bool act = kf < A;
-        T d = AddrOf<W>::make(0, 0);
-        double v = 0.0;
-        int g = 0, rk = 0;
-        u64 a0 = 0, a1 = 0;
-        u32 k = 0;
-        if (act) {
-            int lo = 0;
-            for (int stp = top; stp > 0; stp >>= 1) {
-                const int nx = lo + stp;
-                if (nx < nS && (i64)info[2 * (w0_ + nx)] <= kf) lo = nx;
+        T d[NR];
+        double v[NR];
+        int g[NR], rk[NR];
+        u64 pa0[NR], pa1[NR];
+        u32 kk[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const i64 kf = base + (i64)r * BS + tid;
+            d[r] = AddrOf<W>::make(0, 0);
+            v[r] = 0.0;
+            g[r] = -1;
+            rk[r] = 0;
+            pa0[r] = pa1[r] = 0;
+            kk[r] = 0;
+            if (kf < A) {
+                int lo = 0;
+                for (int stp = top; stp > 0; stp >>= 1) {
+                    const int nx = lo + stp;
+                    if (nx < nS && (i64)info[2 * (w0_ + nx)] <= kf) lo = nx;
+                }
+                const int w = w0_ + lo;
+                const u32 k = (u32)(kf - (i64)info[2 * w]);
+                const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
+                const i64 e = (i64)b * I.cap_t + perm[w];
+                const u64 a0 = I.tab_a[par][0][e];
+                const u64 a1 = W == 2 ? I.tab_a[par][1][e] : 0;
+                const double c = I.tab_v[par][e];
+                const T a = AddrOf<W>::make(a0, a1);
+                double h, q;
+                T dd;
+                if (MODEL == 0) {
+                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
+                    const u32 k3 = k & 3;
+                    const u32 rw = k3 == 0 ? rr.x : k3 == 1 ? rr.y : k3 == 2 ? rr.z : rr.w;
+                    const T st = run_starts(a);
+                    const int o = popc(st);
+                    dd = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)(2 * o)), h);
+                    q = (double)(2 * o) / (double)cnt;
+                } else {
+                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
+                    const bool odd = (k & 1) != 0;
+                    const u32 x0 = odd ? rr.z : rr.x, x1 = odd ? rr.w : rr.y;
+                    i64 qn;
+                    if (narrow)
+                        dd = AddrOf<W>::make((u64)mom_stochastic<u32>(I.mc, (u32)a0, x0, x1, h, qn, lut), 0);
+                    else
+                        dd = mom_stochastic(I.mc, a, x0, x1, h, qn, lut);
+                    q = (double)qn / (double)cnt;
+                }
+                d[r] = dd;
+                v[r] = ((-(I.dtau * h)) * c) * q;
+                pa0[r] = a0;
+                pa1[r] = a1;
+                kk[r] = k;
+                g[r] = out.group(dd);
+                rk[r] = out.rank(g[r]);
             }
-            const int w = w0_ + lo;
-            k = (u32)(kf - (i64)info[2 * w]);
-            const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
-            const i64 e = (i64)b * I.cap_t + perm[w];
-            a0 = I.tab_a[par][0][e];
-            a1 = W == 2 ? I.tab_a[par][1][e] : 0;
-            const double c = I.tab_v[par][e];
-            const T a = AddrOf<W>::make(a0, a1);
-            double h, q;
-            if (MODEL == 0) {
-                const R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
-                const u32 kk = k & 3;
-                const u32 rw = kk == 0 ? r.x : kk == 1 ? r.y : kk == 2 ? r.z : r.w;
-                const T st = run_starts(a);
-                const int o = popc(st);
-                d = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)(2 * o)), h);
-                q = (double)(2 * o) / (double)cnt;
-            } else {
-                const R4 r = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
-                const bool odd = (k & 1) != 0;
-                i64 qn;
-                d = mom_stochastic(I.mc, a, odd ? r.z : r.x, odd ? r.w : r.y, h, qn);
-                q = (double)qn / (double)cnt;
-            }
-            v = ((-(I.dtau * h)) * c) * q;
-            g = out.group(d);
-            rk = out.rank(g);
         }
         out.reserve();
-        if (act) out.put(g, rk, d, v, a0, a1, k);
+#pragma unroll
+        for (int r = 0; r < NR; r++)
+            if (g[r] >= 0) out.put(g[r], rk[r], d[r], v[r], pa0[r], pa1[r], kk[r]);
     }
 }
 
@@ -796,6 +822,8 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
     // w-th entry in that order and perm[w] its table index
     u32 *info = (u32 *)(smem + 160 * 8);
     u32 *perm = info + 2 * I.cap_t;
+    unsigned char *lut = (unsigned char *)(perm + I.cap_t);  // select table, 2048 bytes
+    for (int i = tid; i < 2048; i += BS) lut[i] = select_lut_entry(i);
     const int nS = I.tab_n[par][b];
     const i64 tb = (i64)b * I.cap_t;
     const int chunk = (nS + BS - 1) / BS;
@@ -858,7 +886,7 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
     __syncthreads();
     mark(6);
     spawn_exact<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, info, perm, utot);
-    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, nS - (int)tot_e, info, perm, atot);
+    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, nS - (int)tot_e, info, perm, atot, lut);
     mark(7);
 }
 
