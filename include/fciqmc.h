@@ -83,6 +83,12 @@ typedef struct {
 #define FQ_FLAG_DUMP_SPAWNS 1   /* record every spawn event (parity testing)      */
 #define FQ_FLAG_DUMP_MERGED 2   /* record every merged pre-compression amplitude  */
 #define FQ_FLAG_PHASE_TIMING 4  /* accumulate per-phase timers (diagnostics)      */
+/* Sampled dumps: with FQ_FLAG_DUMP_SAMPLE(k), k in 1..20, the dumps keep only
+ * the spawn events whose destination, and the merged amplitudes whose
+ * address, fall in a fixed sample of about 2^-k of all addresses (bits
+ * 24..24+k-1 of the address hash are zero).  Every event into a sampled
+ * address is kept, so sums per sampled address can be checked. */
+#define FQ_FLAG_DUMP_SAMPLE(k) ((k) << 8)
 
 /* Algorithm parameters.  dtau: time step (Sec. 3.1); target_walkers: N_t;
  * zeta, xi: shift damping and forcing (Eq. shift-update; defaults 0.08 and

@@ -378,7 +378,12 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     R.log2G = R.two_pass ? std::min(6, std::max(4, R.log2B - 8)) : R.log2B;
     R.log2SUB = 6;
     R.cap_c = R.two_pass ? cap((double)L.spawn_capacity / (double)((i64)1 << (R.log2G + R.log2SUB))) + 256 : 1;
-    R.dump_cap = (p->flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) ? L.spawn_capacity + L.table_capacity : 0;
+    {
+        // sampled dumps keep about 2^-k of the events; twice that plus slack
+        const int k = (p->flags >> 8) & 31;
+        const i64 all = L.spawn_capacity + L.table_capacity;
+        R.dump_cap = (p->flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) ? (k ? 2 * (all >> k) + 65536 : all) : 0;
+    }
     R.nsq = (h->N + 2) * (h->N + 2) + 8;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };

@@ -39,6 +39,21 @@ template <class T> __device__ __forceinline__ int runlen(T a, int s) { return ct
 
 template <class T> __device__ __forceinline__ T run_starts(T a) { return a & ~shl(a, 1); }
 
+// (u/2) sum_j n_j (n_j - 1): a run of n ones holds n - k positions whose k
+// higher neighbours are all ones, so sum_j n_j (n_j - 1) / 2 is the sum over
+// k >= 1 of popc(a & a>>1 & ... & a>>k); the loop runs as many times as the
+// longest run.
+template <class T> __device__ __forceinline__ double real_diag_runs(const ModelConst &C, T a)
+{
+    i64 s = 0;
+    T x = a & shr(a, 1);
+    while (!is_zero(x)) {
+        s += popc(x);
+        x = x & shr(x, 1);
+    }
+    return (0.5 * C.u) * (double)(2 * s);
+}
+
 template <class T> __device__ __forceinline__ double real_diag(const ModelConst &C, T a)
 {
     T st = run_starts(a);
@@ -126,6 +141,29 @@ template <class T> __device__ __forceinline__ MomP<T> mom_parent(const ModelCons
     }
     P.o_odd = oo;
     return P;
+}
+
+// Diagonal element in one pass over the M modes in order (a trip count the
+// same for every lane; eps[j] is a uniform, scalar load).  Empty modes add
+// eps_j * 0 = +-0 to the kinetic sum, which leaves it unchanged (the sum
+// starts at +0 and never becomes -0), so the result equals the sum over the
+// occupied modes in ascending order bit for bit.
+template <class T> __device__ __forceinline__ double mom_diag_modes(const ModelConst &C, T a)
+{
+    T zz = (~a & mask_below<T>(C.nb)) | one_at<T>(C.nb);  // separators, then the end
+    double kin = 0.0;
+    int sq = 0, prev = -1;
+    for (int j = 0; j < C.M; j++) {
+        const int zp = ctz(zz);
+        zz = zz & ~one_at<T>(zp);
+        const int n = zp - prev - 1;
+        prev = zp;
+        kin = kin + C.eps[j] * (double)n;
+        sq += n * n;
+    }
+    const i64 N = C.N;
+    const double pot = C.coef * (double)(2 * N * N - N - (i64)sq);
+    return kin + pot;
 }
 
 template <class T> __device__ __forceinline__ double mom_diag(const ModelConst &C, const MomP<T> &P)

@@ -115,6 +115,15 @@ __device__ __forceinline__ void set_error(Ctrl *c, int code, int bucket)
 // an instance does no work once it has failed or has reached its stop step
 // (instances of a batch stop independently; all kernels of one step see the
 // same step number, which only the finalize kernel advances)
+// Parity dumps may keep a sample of the addresses: with k = flags bits 8..12
+// (0 = keep all), an address is kept when bits 24 .. 24+k-1 of its hash are
+// zero, a fixed 2^-k fraction independent of the bucket and LDS slot bits.
+__device__ __forceinline__ bool dump_keeps(int flags, u64 h)
+{
+    const int k = (flags >> 8) & 31;
+    return k == 0 || ((h >> 24) & ((1ull << k) - 1)) == 0;
+}
+
 __device__ __forceinline__ int halted(Ctrl *c)
 {
     const int e = __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -339,7 +348,7 @@ template <int W> struct SpawnOut {
             if (pos < I.cap_s) store_rec<W>(I.slab[out_par], (i64)g * I.cap_s + pos, d, v);
             else set_error(I.ctrl, FQE_CAP_SLAB, g);
         }
-        if (I.flags & 1) {
+        if ((I.flags & 1) && dump_keeps(I.flags, addr_hash(d))) {
             i64 di = atomicAdd((unsigned long long *)&I.ctrl->dump_spawn_n, 1ull);
             if (di < I.dump_cap) {
                 I.dsp_parent[di * W] = pa0;
@@ -598,6 +607,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         }
     };
     const int out_par = 1 - p;
+    const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
     const int spt = slots / BS;  // candidate slots per thread (contiguous), <= 8
 
     // candidate survivors of this thread: address words and value (0 = none)
@@ -626,8 +636,8 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             double c = I.tab_v[p][tb + i];
             T a = AddrOf<W>::make(a0, a1);
             double hii;
-            if (MODEL == 0) hii = real_diag(I.mc, a);
-            else hii = mom_diag(I.mc, mom_parent(I.mc, a));
+            if (MODEL == 0) hii = narrow ? real_diag_runs<u32>(I.mc, (u32)a0) : real_diag_runs(I.mc, a);
+            else hii = narrow ? mom_diag_modes<u32>(I.mc, (u32)a0) : mom_diag_modes(I.mc, a);
             double g = 1.0 + I.dtau * (S - hii);
             lds_add<W>(L, I, a0, a1, c * g, b, nprobe);
         }
@@ -676,7 +686,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             if (occ) {
                 used++;
                 double w = from_fixed(L.lo[s], L.hi[s]);
-                if (I.flags & 2) {
+                if ((I.flags & 2) && dump_keeps(I.flags, addr_hash(AddrOf<W>::make(a0, a1)))) {
                     i64 di = atomicAdd((unsigned long long *)&ctrl->dump_merged_n, 1ull);
                     if (di < I.dump_cap) {
                         I.dmg_addr[di * W] = a0;
