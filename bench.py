@@ -39,8 +39,8 @@ WORKLOADS = {
                table_capacity=19_500_000, spawn_capacity=200_000_000, buckets=16384,
                lds_slots=2048, block=512, spawn_block=256, warmup=3000, steps=1000),
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
-               table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=0,
-               lds_slots=4096, block=1024, spawn_block=256, warmup=6000, steps=1000),
+               table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=16384,
+               lds_slots=2048, block=512, spawn_block=256, warmup=6000, steps=1000),
     "c1": dict(cfg="c1", name="real1d_M6_N6_u6_dtau1e-3_Nt1e3",
                table_capacity=1024, spawn_capacity=8192, buckets=0, lds_slots=0, block=0,
                spawn_block=0, warmup=0, steps=10_000),

@@ -203,6 +203,38 @@ template <class T> __device__ __forceinline__ i64 mom_m(const MomP<T> &P, int M)
     return np * (M / 2) - (i64)P.o_odd * (P.o - P.o_odd);
 }
 
+// bit i = parity of the set bits of x in [0, i]
+__device__ __forceinline__ u32 prefix_xor(u32 x)
+{
+    x ^= x << 1; x ^= x << 2; x ^= x << 4; x ^= x << 8; x ^= x << 16;
+    return x;
+}
+__device__ __forceinline__ u64 prefix_xor(u64 x)
+{
+    x ^= x << 1; x ^= x << 2; x ^= x << 4; x ^= x << 8; x ^= x << 16; x ^= x << 32;
+    return x;
+}
+__device__ __forceinline__ U128 prefix_xor(U128 x)
+{
+    const u64 lo = prefix_xor(x.lo);
+    const u64 hi = prefix_xor(x.hi) ^ ((__popcll(x.lo) & 1) ? ~0ull : 0ull);
+    return U128{lo, hi};
+}
+
+// Column size m of a momentum-space parent without a loop: the parity of
+// the mode that starts at bit s is the parity of the separators below s.
+template <class T> __device__ __forceinline__ i64 mom_col_size(const ModelConst &C, T a)
+{
+    const int M = C.M;
+    const T st = run_starts(a);
+    const int o = popc(st);
+    const i64 np = (i64)o * (o - 1) / 2 + popc(st & shr(a, 1));
+    if (M & 1) return np * ((M - 1) / 2);
+    const T par = shl(prefix_xor(~a & mask_below<T>(C.nb)), 1);  // parity of the mode at each bit
+    const int o_odd = popc(st & par);
+    return np * (M / 2) - (i64)o_odd * (o - o_odd);
+}
+
 template <class T> __device__ __forceinline__ T del_bit(T a, int x)
 {
     return (a & mask_below<T>(x)) | shl(shr(a, x + 1), x);

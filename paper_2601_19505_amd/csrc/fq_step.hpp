@@ -284,7 +284,8 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
 {
     i64 m;
     if (MODEL == 0) m = 2 * popc(run_starts(a));
-    else m = mom_m(mom_parent(I.mc, a), I.mc.M);
+    else if (W == 1 && I.mc.nb <= 32) m = mom_col_size<u32>(I.mc, (u32)word0(a));
+    else m = mom_col_size(I.mc, a);
     double ac = fabs(c);
     exact = (m == 0) || ac >= I.t_rel * (double)m;
     if (exact) {
@@ -775,8 +776,15 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         }
     }
     if (tid == 0) { L.misc[40] = 0; L.misc[41] = 0; }
+    // exact wave reduction first: one LDS accumulation per wave instead of
+    // one per thread on the same address
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const u64 x = __shfl_down(nlo, o, 64), y = __shfl_down(nhi, o, 64);
+        add128(nlo, nhi, x, y);
+    }
     __syncthreads();
-    if (nlo | nhi) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
+    if ((tid & 63) == 0 && (nlo | nhi)) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
     __syncthreads();
     if (tid == 0) {
         I.tab_n[out_par][b] = (int)total;
