@@ -267,7 +267,8 @@ int ilog2(i64 x)
     return r;
 }
 
-size_t rec_bytes(int W) { return W == 1 ? 16 : 24; }
+// bytes per spawn record (see store_rec)
+size_t rec_bytes(int W, int nb) { return W == 2 ? 24 : (nb <= 32 ? 12 : 16); }
 
 // merge kernel: the LDS hash table (keys, 128-bit accumulators, W = 2 slot
 // states) and the scratch words
@@ -299,6 +300,7 @@ struct Exec {
 struct Resolved {
     int W, nb, B, log2B, slots, block, spawn_block, two_pass, log2G, log2SUB;
     i64 cap_t, cap_s, cap_c, dump_cap;
+    size_t rec, slab_bytes;  // bytes per spawn record; bytes of one slab
     size_t off_ctrl, off_inst, off_iptr, off_pmap, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
         off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], off_coarse,
@@ -385,6 +387,10 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
         R.dump_cap = (p->flags & (FQ_FLAG_DUMP_SPAWNS | FQ_FLAG_DUMP_MERGED)) ? (k ? 2 * (all >> k) + 65536 : all) : 0;
     }
     R.nsq = (h->N + 2) * (h->N + 2) + 8;
+    // a slab also stages a whole table (8W + 8 bytes per entry) for
+    // set_state, get_state and copy_state
+    R.rec = rec_bytes(R.W, R.nb);
+    R.slab_bytes = std::max(R.rec * (size_t)R.B * R.cap_s, (size_t)(8 * R.W + 8) * (size_t)R.B * R.cap_t + 256);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     R.off_ctrl = take(sizeof(Ctrl));
@@ -408,10 +414,10 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
         R.off_tab_a[q][1] = R.W == 2 ? take(sizeof(u64) * tn) : 0;
         R.off_tab_v[q] = take(sizeof(double) * tn);
         R.off_tab_n[q] = take(sizeof(int) * R.B);
-        R.off_slab[q] = take(rec_bytes(R.W) * (size_t)R.B * R.cap_s);
+        R.off_slab[q] = take(R.slab_bytes);
         R.off_slab_n[q] = take(sizeof(int) * R.B);
     }
-    R.off_coarse = take(rec_bytes(R.W) * (size_t)R.cap_c << (R.log2G + R.log2SUB));
+    R.off_coarse = take(R.rec * (size_t)R.cap_c << (R.log2G + R.log2SUB));
     R.off_coarse_n = take(sizeof(int) << (R.log2G + R.log2SUB));
     const i64 dc = std::max<i64>(R.dump_cap, 1);
     R.off_dsp_parent = take(sizeof(u64) * R.W * dc);
@@ -666,6 +672,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     I.log2G = R.log2G;
     I.log2SUB = R.log2SUB;
     I.cap_c = R.cap_c;
+    I.rec = (int)R.rec;
     I.coarse = q->ws + R.off_coarse;
     I.coarse_n = (int *)(q->ws + R.off_coarse_n);
     I.spart[0] = (SpawnPart *)(q->ws + R.off_spart[0]);
@@ -800,7 +807,7 @@ int fq_set_state(fq_handle *q, const uint64_t *addrs, const double *vals, int64_
     for (size_t i = 1; i < keys.size(); i++)
         if (keys[i] == keys[i - 1]) { q->err = "duplicate address in state"; return FQ_EINVAL; }
     if (!valid_address(ref_addr, W, q->h.M, q->h.N)) { q->err = "invalid reference address"; return FQ_EINVAL; }
-    if ((size_t)n * (8 * W + 8) > rec_bytes(W) * (size_t)R.B * R.cap_s || n > (i64)R.B * R.cap_t) {
+    if ((size_t)n * (8 * W + 8) > R.slab_bytes || n > (i64)R.B * R.cap_t) {
         q->err = "state larger than the workspace capacity";
         return FQ_ECAPACITY;
     }
@@ -989,7 +996,7 @@ int fq_get_state(fq_handle *q, uint64_t *addrs, double *vals, int64_t cap, int64
     u64 *oa = (u64 *)(buf + 256);
     const i64 total_cap = (i64)R.B * R.cap_t;
     double *ov = (double *)(oa + (size_t)W * total_cap);
-    if (256 + (8 * W + 8) * (size_t)total_cap > rec_bytes(W) * (size_t)R.B * R.cap_s) {
+    if (256 + (8 * W + 8) * (size_t)total_cap > R.slab_bytes) {
         q->err = "slab too small to stage the table";
         return FQ_ECAPACITY;
     }
@@ -1072,7 +1079,7 @@ int fq_copy_state(fq_handle *dst, fq_handle *src, void *stream)
     if (rc) return rc;
     if (c.error) { dst->err = "copy_state: source is in an error state"; return FQ_EINVAL; }
     const i64 nmax = (i64)src->R.B * src->R.cap_t;
-    if (256 + (8 * W + 8) * (size_t)nmax > rec_bytes(W) * (size_t)dst->R.B * dst->R.cap_s) {
+    if (256 + (8 * W + 8) * (size_t)nmax > dst->R.slab_bytes) {
         dst->err = "copy_state: destination slab too small to stage the source table";
         return FQ_ECAPACITY;
     }

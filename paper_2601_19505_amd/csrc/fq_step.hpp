@@ -101,7 +101,8 @@ struct Inst {
     SpawnPart *spart[2]; // [row parity][B]
     // two-pass spawn partition (B > 64): G = 2^log2G groups of B/G buckets,
     // each with SUB = 2^log2SUB coarse sub-slabs of cap_c records
-    int two_pass, log2G, log2SUB, pad2;
+    int two_pass, log2G, log2SUB;
+    int rec;  // bytes per spawn record: 12 (one address word that fits 32 bits), 16 or 24
     i64 cap_c;
     char *coarse;
     int *coarse_n;
@@ -140,31 +141,49 @@ template <> struct Rec<2> {
     double v;
 };
 
-template <int W> __device__ __forceinline__ void store_rec(char *base, i64 i, typename AddrOf<W>::T d, double v);
-template <> __device__ __forceinline__ void store_rec<1>(char *base, i64 i, u64 d, double v)
+// Spawn records in the slabs: address words then the value.  When the
+// address fits 32 bits (one word, N+M-1 <= 32) a record is three 32-bit words
+// (12 bytes, rec = 12); otherwise 16 or 24 bytes.  `base` is the start of a
+// slab or sub-slab, i the record index.
+template <int W> __device__ __forceinline__ void store_rec(int rec, char *base, i64 i, typename AddrOf<W>::T d, double v);
+template <> __device__ __forceinline__ void store_rec<1>(int rec, char *base, i64 i, u64 d, double v)
 {
-    Rec<1> *r = (Rec<1> *)base + i;
-    ulonglong2 x;
-    x.x = d;
-    x.y = dbits(v);
-    *(ulonglong2 *)r = x;
+    const u64 vb = dbits(v);
+    if (rec == 12) {
+        uint3 x;
+        x.x = (u32)d;
+        x.y = (u32)vb;
+        x.z = (u32)(vb >> 32);
+        *(uint3 *)(base + 12 * i) = x;
+    } else {
+        ulonglong2 x;
+        x.x = d;
+        x.y = vb;
+        *((ulonglong2 *)base + i) = x;
+    }
 }
-template <> __device__ __forceinline__ void store_rec<2>(char *base, i64 i, U128 d, double v)
+template <> __device__ __forceinline__ void store_rec<2>(int, char *base, i64 i, U128 d, double v)
 {
     Rec<2> *r = (Rec<2> *)base + i;
     r->a0 = d.lo;
     r->a1 = d.hi;
     r->v = v;
 }
-template <int W> __device__ __forceinline__ void load_rec(const char *base, i64 i, u64 &a0, u64 &a1, double &v);
-template <> __device__ __forceinline__ void load_rec<1>(const char *base, i64 i, u64 &a0, u64 &a1, double &v)
+template <int W> __device__ __forceinline__ void load_rec(int rec, const char *base, i64 i, u64 &a0, u64 &a1, double &v);
+template <> __device__ __forceinline__ void load_rec<1>(int rec, const char *base, i64 i, u64 &a0, u64 &a1, double &v)
 {
-    ulonglong2 x = *((const ulonglong2 *)base + i);
-    a0 = x.x;
     a1 = 0;
-    v = bitsd(x.y);
+    if (rec == 12) {
+        const uint3 x = *(const uint3 *)(base + 12 * i);
+        a0 = x.x;
+        v = bitsd(((u64)x.z << 32) | x.y);
+    } else {
+        const ulonglong2 x = *((const ulonglong2 *)base + i);
+        a0 = x.x;
+        v = bitsd(x.y);
+    }
 }
-template <> __device__ __forceinline__ void load_rec<2>(const char *base, i64 i, u64 &a0, u64 &a1, double &v)
+template <> __device__ __forceinline__ void load_rec<2>(int, const char *base, i64 i, u64 &a0, u64 &a1, double &v)
 {
     const Rec<2> *r = (const Rec<2> *)base + i;
     a0 = r->a0;
@@ -343,10 +362,10 @@ template <int W> struct SpawnOut {
         const i64 pos = gbase()[g] + rk;
         if (I.two_pass) {
             const i64 cs = ((i64)g << I.log2SUB) + sub;
-            if (pos < I.cap_c) store_rec<W>(I.coarse, cs * I.cap_c + pos, d, v);
+            if (pos < I.cap_c) store_rec<W>(I.rec, I.coarse, cs * I.cap_c + pos, d, v);
             else set_error(I.ctrl, FQE_CAP_SLAB, g);
         } else {
-            if (pos < I.cap_s) store_rec<W>(I.slab[out_par], (i64)g * I.cap_s + pos, d, v);
+            if (pos < I.cap_s) store_rec<W>(I.rec, I.slab[out_par], (i64)g * I.cap_s + pos, d, v);
             else set_error(I.ctrl, FQE_CAP_SLAB, g);
         }
         if ((I.flags & 1) && dump_keeps(I.flags, addr_hash(d))) {
@@ -644,7 +663,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         }
         if (timing) { __syncthreads(); mark(1); }
         const int ns = min(I.slab_n[p][b], (int)I.cap_s);
-        const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)sizeof(Rec<W>);
+        const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)I.rec;
         for (int i0 = 0; i0 < ns; i0 += 4 * BS) {
             // four independent record loads in flight per thread
             u64 x0[4], x1[4];
@@ -652,7 +671,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int i = i0 + e * BS + tid;
-                if (i < ns) load_rec<W>(sb, i, x0[e], x1[e], xv[e]);
+                if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
             }
 #pragma unroll
             for (int e = 0; e < 4; e++) {
@@ -930,7 +949,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
     const int log2F = I.log2B - I.log2G;
     const int F = 1 << log2F;
     const int n = min(I.coarse_n[cs], (int)I.cap_c);
-    const char *src = I.coarse + (i64)cs * I.cap_c * (i64)sizeof(Rec<W>);
+    const char *src = I.coarse + (i64)cs * I.cap_c * (i64)I.rec;
     for (int r0 = 0; r0 < n; r0 += BS * RPT) {
         if (tid < F) cnt[tid] = 0;
         __syncthreads();
@@ -942,7 +961,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             const int i = r0 + e * BS + tid;
             lb[e] = -1;
             if (i < n) {
-                load_rec<W>(src, i, a0[e], a1[e], v[e]);
+                load_rec<W>(I.rec, src, i, a0[e], a1[e], v[e]);
                 lb[e] = (int)(bucket_of(addr_hash(AddrOf<W>::make(a0[e], a1[e])), I.log2B) & (u32)(F - 1));
             }
         }
@@ -960,7 +979,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             if (lb[e] < 0) continue;
             const i64 pos = base[lb[e]] + rk[e];
             const i64 d = ((i64)g << log2F) + lb[e];
-            if (pos < I.cap_s) store_rec<W>(I.slab[q], d * I.cap_s + pos, AddrOf<W>::make(a0[e], a1[e]), v[e]);
+            if (pos < I.cap_s) store_rec<W>(I.rec, I.slab[q], d * I.cap_s + pos, AddrOf<W>::make(a0[e], a1[e]), v[e]);
             else set_error(ctrl, FQE_CAP_SLAB, (int)d);
         }
         __syncthreads();
