@@ -79,7 +79,7 @@ __global__ __launch_bounds__(1024) void k_finalize(const Inst *const *insts)
 #define FQ_PART_BS 1024
 #endif
 #ifndef FQ_PART_RPT
-#define FQ_PART_RPT 8
+#define FQ_PART_RPT 2
 #endif
 constexpr int PART_BS = FQ_PART_BS;    // threads per workgroup of the second pass
 constexpr int PART_RPT = FQ_PART_RPT;  // records per thread and round
