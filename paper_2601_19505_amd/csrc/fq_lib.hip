@@ -159,50 +159,42 @@ __global__ void k_take_norm(const Inst *Ip)
 }
 
 // column of the reference address: entry 0 is the diagonal, then the
-// off-diagonal entries; bucket of every destination
+// off-diagonal entries in column order; bucket of every destination
 template <int W, int MODEL>
 __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *ob, int *on, int cap)
 {
     const Inst &I = *Ip;
     typedef typename AddrOf<W>::T T;
+    __shared__ unsigned char lut[2048];
+    for (int i = threadIdx.x; i < 2048; i += blockDim.x) lut[i] = select_lut_entry(i);
+    __syncthreads();
     if (threadIdx.x != 0) return;
     const T a = AddrOf<W>::make(r0, r1);
+    const T st = run_starts(a);
+    const int o = popc(st);
     double hd;
     i64 m;
-    MomP<T> P = mom_parent(I.mc, a);
     if (MODEL == 0) {
-        hd = real_diag(I.mc, a);
-        m = 2 * popc(run_starts(a));
+        hd = real_diag_runs(I.mc, a);
+        m = 2 * o;
     } else {
-        hd = mom_diag(I.mc, P);
-        m = mom_m(P, I.mc.M);
+        hd = mom_diag_modes(I.mc, a);
+        m = mom_col_size(I.mc, a);
     }
     if (m + 1 > cap) { *on = -1; return; }
     oa[0] = r0;
     oa[1] = r1;
     oh[0] = hd;
     ob[0] = (int)bucket_of(addr_hash(a), I.log2B);
-    int k = 1;
-    const T st = run_starts(a);
-    const int o = popc(st);
-    PairIt<T> it;
-    if (MODEL == 1 && m > 0) mom_it_init(P, I.mc.M, 0, it);
     for (i64 e = 0; e < m; e++) {
         double h;
-        T d;
-        if (MODEL == 0) {
-            d = real_entry(I.mc, a, st, o, (int)e, h);
-        } else {
-            if (e > 0) mom_it_next(P, I.mc.M, it);
-            d = mom_move(I.mc, P, it.pa, it.pb, it.sa, it.sb, it.di, h);
-        }
-        oa[2 * k] = word0(d);
-        oa[2 * k + 1] = word1(d);
-        oh[k] = h;
-        ob[k] = (int)bucket_of(addr_hash(d), I.log2B);
-        k++;
+        const T d = MODEL == 0 ? real_entry(I.mc, a, st, o, (int)e, h) : mom_column_entry(I.mc, a, (int)e, h, lut);
+        oa[2 * (e + 1)] = word0(d);
+        oa[2 * (e + 1) + 1] = word1(d);
+        oh[e + 1] = h;
+        ob[e + 1] = (int)bucket_of(addr_hash(d), I.log2B);
     }
-    *on = k;
+    *on = (int)m + 1;
 }
 
 // copy table[parity] into contiguous arrays

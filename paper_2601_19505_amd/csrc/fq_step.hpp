@@ -382,124 +382,17 @@ template <int W> struct SpawnOut {
     }
 };
 
-// Exact columns (Sec. 7.1): the m entries of each exact parent in column
-// order, cut into units of 4 entries; units [0, u_hi) of the nE exact
-// entries (offsets in info[2 i]).  Blocked assignment: thread t walks a
-// contiguous range of units, so a parent is decoded once and the column
-// iterator carries over between its units.
-template <int W, int MODEL, int BS>
-__device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const int b, const int par,
-                                            const u32 spawn_step, const int nE, const u32 *info, const u32 *perm,
-                                            const i64 u_hi)
-{
-    typedef typename AddrOf<W>::T T;
-    constexpr int MAXM = MODEL == 1 ? 16 : 32;
-    const int tid = threadIdx.x;
-    const SpawnOut<W> out(I, L, par, b);
-    const double dtau = I.dtau;
-    const i64 nu = u_hi;
-    if (nu <= 0) return;
-    const i64 u_beg = nu * tid / BS, u_end = nu * (tid + 1) / BS;
-    const i64 rounds = (nu + BS - 1) / BS;
-    i64 u = u_beg;
-    int cur = -1;     // current parent
-    i64 cur_end = 0;  // first unit of the next parent
-    i64 cur_off = 0;
-    u32 cnt = 0;
-    double c = 0.0;
-    u64 a0 = 0, a1 = 0;
-    T st;
-    int o = 0;
-    MomD<T, MAXM> D;
-    PairIt<T> it;
-    for (i64 rr = 0; rr < rounds; rr++) {
-        out.begin();
-        T d0, d1, d2, d3;
-        double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-        int nk = 0;
-        u32 k0 = 0;
-        if (u < u_end) {
-            if (u >= cur_end) {
-                // parent holding unit u: binary search first, then walk forward
-                int i;
-                if (cur < 0) {
-                    int lo_i = 0, hi_i = nE - 1;
-                    while (lo_i < hi_i) {
-                        int mid = (lo_i + hi_i + 1) >> 1;
-                        if ((i64)info[2 * mid] <= u) lo_i = mid; else hi_i = mid - 1;
-                    }
-                    i = lo_i;
-                } else {
-                    i = cur + 1;
-                    while (i + 1 < nE && (i64)info[2 * (i + 1)] <= u) i++;
-                }
-                cur = i;
-                cur_off = info[2 * i];
-                cur_end = i + 1 < nE ? (i64)info[2 * (i + 1)] : u_hi;
-                cnt = info[2 * i + 1] & 0x7fffffffu;
-                const i64 e = (i64)b * I.cap_t + perm[i];
-                a0 = I.tab_a[par][0][e];
-                a1 = W == 2 ? I.tab_a[par][1][e] : 0;
-                c = I.tab_v[par][e];
-                const T a = AddrOf<W>::make(a0, a1);
-                if (MODEL == 0) {
-                    st = run_starts(a);
-                    o = popc(st);
-                } else {
-                    D = mom_decode_packed<T, MAXM>(I.mc, a);
-                    mom_it_init(D.P, I.mc.M, (i64)(4 * (u - cur_off)), it);
-                }
-            }
-            const u32 qu = (u32)(u - cur_off);
-            k0 = 4 * qu;
-            nk = (int)min(cnt - k0, 4u);
-            if (MODEL == 0) {
-                const T a = AddrOf<W>::make(a0, a1);
-                auto gen = [&](int e, T &dd, double &vv) {
-                    double h;
-                    dd = real_entry(I.mc, a, st, o, (int)(k0 + e), h);
-                    vv = (-(dtau * h)) * c;
-                };
-                gen(0, d0, v0);
-                if (nk > 1) gen(1, d1, v1);
-                if (nk > 2) gen(2, d2, v2);
-                if (nk > 3) gen(3, d3, v3);
-            } else {
-                const int M = I.mc.M;
-                auto gen = [&](T &dd, double &vv) {
-                    double h;
-                    dd = mom_move_d(I.mc, D, it.pa, it.pb, it.sa, it.sb, it.di, h);
-                    vv = (-(dtau * h)) * c;
-                    mom_it_next(D.P, M, it);
-                };
-                gen(d0, v0);
-                if (nk > 1) gen(d1, v1);
-                if (nk > 2) gen(d2, v2);
-                if (nk > 3) gen(d3, v3);
-            }
-            u++;
-        }
-        int g0 = 0, g1 = 0, g2 = 0, g3 = 0, rk0 = 0, rk1 = 0, rk2 = 0, rk3 = 0;
-        if (nk > 0) { g0 = out.group(d0); rk0 = out.rank(g0); }
-        if (nk > 1) { g1 = out.group(d1); rk1 = out.rank(g1); }
-        if (nk > 2) { g2 = out.group(d2); rk2 = out.rank(g2); }
-        if (nk > 3) { g3 = out.group(d3); rk3 = out.rank(g3); }
-        out.reserve();
-        if (nk > 0) out.put(g0, rk0, d0, v0, a0, a1, k0);
-        if (nk > 1) out.put(g1, rk1, d1, v1, a0, a1, k0 + 1);
-        if (nk > 2) out.put(g2, rk2, d2, v2, a0, a1, k0 + 2);
-        if (nk > 3) out.put(g3, rk3, d3, v3, a0, a1, k0 + 3);
-    }
-}
-
-// Stochastic spawns (Sec. 3.2, matrix compression): ceil|c| attempts per
-// parent, each an independent draw.  The A attempts of the nS stochastic
-// entries (permuted indices w0_ .. w0_+nS-1, attempt offsets in info[2 w])
-// are enumerated flat: in each round thread t takes attempts
+// Spawns of all entries (Sec. 3.2, matrix compression; Sec. 7.1, exact
+// columns): an exact entry has m attempts, attempt k being column entry k; a
+// stochastic entry has ceil|c| attempts, each an independent draw.  The A
+// attempts of the nS entries (permuted indices w0_ .. w0_+nS-1, exact entries
+// first, attempt offsets in info[2 w], count word with the exact flag in
+// info[2 w + 1]) are enumerated flat: in each round thread t takes attempts
 // base + r BS + t (r < NR), finds each attempt's parent by a binary search
 // with a fixed number of steps and generates the record with branch-free
-// code, so all lanes of a wave do the same work.  NR records per thread and
-// round make the runs appended to each destination group longer.
+// code, so all lanes of a wave do the same work (only the one round that
+// holds the boundary mixes the two kinds).  NR records per thread and round
+// make the runs appended to each destination group longer.
 #ifndef FQ_SPAWN_NR
 #define FQ_SPAWN_NR 4
 #endif
@@ -539,7 +432,8 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 }
                 const int w = w0_ + lo;
                 const u32 k = (u32)(kf - (i64)info[2 * w]);
-                const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
+                const u32 cw = info[2 * w + 1];
+                const u32 cnt = cw & 0x7fffffffu;
                 const i64 e = (i64)b * I.cap_t + perm[w];
                 const u64 a0 = I.tab_a[par][0][e];
                 const u64 a1 = W == 2 ? I.tab_a[par][1][e] : 0;
@@ -547,6 +441,19 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 const T a = AddrOf<W>::make(a0, a1);
                 double h, q;
                 T dd;
+                if (cw >> 31) {
+                    // exact column (Sec. 7.1): attempt k is column entry k, weight 1
+                    if (MODEL == 0) {
+                        const T st = run_starts(a);
+                        dd = real_entry(I.mc, a, st, popc(st), (int)k, h);
+                    } else if (narrow) {
+                        dd = AddrOf<W>::make((u64)mom_column_entry<u32>(I.mc, (u32)a0, (int)k, h, lut), 0);
+                    } else {
+                        dd = mom_column_entry(I.mc, a, (int)k, h, lut);
+                    }
+                    d[r] = dd;
+                    v[r] = (-(I.dtau * h)) * c;
+                } else {
                 if (MODEL == 0) {
                     const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
                     const u32 k3 = k & 3;
@@ -568,6 +475,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 }
                 d[r] = dd;
                 v[r] = ((-(I.dtau * h)) * c) * q;
+                }
                 pa0[r] = a0;
                 pa1[r] = a1;
                 kk[r] = k;
@@ -898,32 +806,24 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
         if (b == 0) ctrl->spawn_par = par;
     }
     __syncthreads();
-    // offsets: units of 4 column entries for the exact entries, attempts for
-    // the stochastic ones, each counted from the first entry of its kind
-    i64 utot, atot;
+    // attempt offsets over all entries in the exact-first order
+    i64 atot;
     {
-        i64 units = 0, atts = 0;
-        for (int i = i0; i < i1; i++) {
-            const i64 cnt = info[2 * i + 1] & 0x7fffffffu;
-            if (i < tot_e) units += (cnt + 3) / 4;
-            else atts += cnt;
-        }
-        i64 ub = block_excl_scan<BS>(units, L.misc, utot);
+        i64 atts = 0;
+        for (int i = i0; i < i1; i++) atts += info[2 * i + 1] & 0x7fffffffu;
         i64 ab = block_excl_scan<BS>(atts, L.misc, atot);
         for (int i = i0; i < i1; i++) {
-            const i64 cnt = info[2 * i + 1] & 0x7fffffffu;
-            if (i < tot_e) { info[2 * i] = (u32)ub; ub += (cnt + 3) / 4; }
-            else { info[2 * i] = (u32)ab; ab += cnt; }
+            info[2 * i] = (u32)ab;
+            ab += info[2 * i + 1] & 0x7fffffffu;
         }
     }
-    if (utot >= ((i64)1 << 32) || atot >= ((i64)1 << 32)) {
+    if (atot >= ((i64)1 << 32)) {
         if (tid == 0) set_error(ctrl, FQE_CAP_SLAB, b);
         return;
     }
     __syncthreads();
     mark(6);
-    spawn_exact<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, info, perm, utot);
-    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, (int)tot_e, nS - (int)tot_e, info, perm, atot, lut);
+    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut);
     mark(7);
 }
 
