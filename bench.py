@@ -51,6 +51,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "step_kernels_mom1d_M16N16_1e8_hbm_bytes.txt")
+
+
+def measured_traffic(fq, kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE and
+    WRITE_SIZE summary (calibrated against a streaming copy), or None when
+    the summary is absent or was taken with other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("# kernel source sha256:")]
+    if not digest or digest[0] != fq.source_digest():
+        return None
+    total, seen = 0.0, set()
+    for i, ln in enumerate(lines):
+        if ln.startswith("void " + kernel + "<") and i + 1 < len(lines):
+            nxt = lines[i + 1].split()
+            if "calibrated" in nxt and nxt[0] in ("FETCH_SIZE", "WRITE_SIZE"):
+                total += float(nxt[nxt.index("calibrated") + 1]) * 1e9
+                seen.add(nxt[0])
+    return total if seen == {"FETCH_SIZE", "WRITE_SIZE"} else None
+
+
 def make_solver(fq, wl, cfg, **over):
     kw = dict(t=cfg["t"], u=cfg["u"], dtau=cfg["dtau"], target_walkers=cfg["target"],
               seed=cfg["seed"], addr_words=cfg["W"], threshold=cfg["theta"],
@@ -342,7 +367,8 @@ def main():
                    "mean_norm": float(st["norm"].mean()), "mean_len": float(st["len"].mean()),
                    "mean_spawns": float(st["spawns"].mean())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(fq, "k_" + dom) if args.workload == "c3" else None,
                      "kernel": "k_" + dom, "mean_kernel_ms": kern[dom]["mean_ms"],
                      "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"]},
         "kernels": kern,

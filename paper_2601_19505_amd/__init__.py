@@ -521,6 +521,21 @@ class Server:
             pass
 
 
+def source_digest():
+    """sha256 of the kernel sources and the C header (identifies the kernels
+    a profile was taken with)."""
+    import hashlib
+    hsh = hashlib.sha256()
+    root = os.path.dirname(HERE)
+    files = sorted(os.path.join(HERE, "csrc", f) for f in os.listdir(os.path.join(HERE, "csrc"))
+                   if f.endswith((".hip", ".hpp")))
+    files.append(os.path.join(root, "include", "fciqmc.h"))
+    for f in files:
+        with open(f, "rb") as fh:
+            hsh.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return hsh.hexdigest()
+
+
 def start_address(model, M, N, W=1):
     """Default starting address: the uniform state in real space, the k = 0
     condensate in momentum space."""

@@ -102,6 +102,8 @@ def main():
     out, factors = summarize(a.dir, a.last, a.copy_bytes, a.copy_kernel)
     if a.title:
         print(f"# {a.title}")
+    from paper_2601_19505_amd import source_digest
+    print(f"# kernel source sha256: {source_digest()}")
     if factors:
         print("# calibration factors (counter KiB * 1024 / bytes of the copy kernel): " +
               ", ".join(f"{k} {v:.4f}" for k, v in factors.items()))
