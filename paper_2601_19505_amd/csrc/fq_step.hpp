@@ -492,6 +492,13 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
 
 // ---------------------------------------------------------------- the step
 
+#ifndef FQ_MERGE_MT
+#define FQ_MERGE_MT 2  // table entries in flight per merge thread
+#endif
+#ifndef FQ_MERGE_MS
+#define FQ_MERGE_MS 4  // spawn records in flight per merge thread
+#endif
+
 // Merge of bucket b for step n+1: the diagonal survivors of table[p] and the
 // spawn records of slab[p] are summed per address in an LDS hash table, the
 // sums are compressed, the projected-energy terms of the bucket's reference
@@ -544,6 +551,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 #pragma unroll
     for (int k = 0; k < 8; k++) { r0[k] = 0; r1[k] = 0; rc[k] = 0.0; }
 
+    int used = 0;  // occupied LDS slots of this thread
     {
         // ------------------------------------------------ 1. merge
         int nprobe = 0;
@@ -558,33 +566,56 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         mark(0);
         const int nt = I.tab_n[p][b];
         const i64 tb = (i64)b * I.cap_t;
-        for (int i = tid; i < nt; i += BS) {
-            u64 a0 = I.tab_a[p][0][tb + i];
-            u64 a1 = W == 2 ? I.tab_a[p][1][tb + i] : 0;
-            double c = I.tab_v[p][tb + i];
-            T a = AddrOf<W>::make(a0, a1);
-            double hii;
-            if (MODEL == 0) hii = narrow ? real_diag_runs<u32>(I.mc, (u32)a0) : real_diag_runs(I.mc, a);
-            else hii = narrow ? mom_diag_modes<u32>(I.mc, (u32)a0) : mom_diag_modes(I.mc, a);
-            double g = 1.0 + I.dtau * (S - hii);
-            lds_add<W>(L, I, a0, a1, c * g, b, nprobe);
-        }
-        if (timing) { __syncthreads(); mark(1); }
         const int ns = min(I.slab_n[p][b], (int)I.cap_s);
         const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)I.rec;
-        for (int i0 = 0; i0 < ns; i0 += 4 * BS) {
-            // four independent record loads in flight per thread
-            u64 x0[4], x1[4];
-            double xv[4];
+        // Loads in flight per thread: the first MT table entries and the
+        // first MS spawn records are requested before any insert, so the
+        // record loads overlap the diagonal computations of the table phase.
+        constexpr int MT = FQ_MERGE_MT, MS = FQ_MERGE_MS;
+        u64 x0[MS], x1[MS];
+        double xv[MS];
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
+        for (int e = 0; e < MS; e++) {
+            const int i = e * BS + tid;
+            if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
+        }
+        for (int i0 = 0; i0 < nt; i0 += MT * BS) {
+            u64 t0[MT], t1[MT];
+            double tc[MT];
+#pragma unroll
+            for (int e = 0; e < MT; e++) {
                 const int i = i0 + e * BS + tid;
-                if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
+                if (i < nt) {
+                    t0[e] = I.tab_a[p][0][tb + i];
+                    t1[e] = W == 2 ? I.tab_a[p][1][tb + i] : 0;
+                    tc[e] = I.tab_v[p][tb + i];
+                }
             }
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
+            for (int e = 0; e < MT; e++) {
+                const int i = i0 + e * BS + tid;
+                if (i < nt) {
+                    const T a = AddrOf<W>::make(t0[e], t1[e]);
+                    double hii;
+                    if (MODEL == 0) hii = narrow ? real_diag_runs<u32>(I.mc, (u32)t0[e]) : real_diag_runs(I.mc, a);
+                    else hii = narrow ? mom_diag_modes<u32>(I.mc, (u32)t0[e]) : mom_diag_modes(I.mc, a);
+                    const double g = 1.0 + I.dtau * (S - hii);
+                    lds_add<W>(L, I, t0[e], t1[e], tc[e] * g, b, nprobe);
+                }
+            }
+        }
+        if (timing) { __syncthreads(); mark(1); }
+        for (int i0 = 0; i0 < ns; i0 += MS * BS) {
+#pragma unroll
+            for (int e = 0; e < MS; e++) {
                 const int i = i0 + e * BS + tid;
                 if (i < ns) lds_add<W>(L, I, x0[e], x1[e], xv[e], b, nprobe);
+            }
+            // next batch
+#pragma unroll
+            for (int e = 0; e < MS; e++) {
+                const int i = i0 + (MS + e) * BS + tid;
+                if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
             }
         }
         __syncthreads();
@@ -602,7 +633,6 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         }
 
         // ------------------------------------------------ 2. compress (per slot, owner thread)
-        int used = 0;
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (k >= spt) break;
@@ -640,7 +670,8 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         for (int k = 0; k < 8; k++)
             if (k < spt) L.lo[tid * spt + k] = dbits(rc[k]);
         mark(3);
-        if (tid == 0) { L.misc[42] = 0; L.misc[43] = 0; L.misc[44] = 0; L.misc[45] = 0; }
+        // 128-bit accumulators: [40,41] norm, [42,43] y.Hc, [44,45] y.c
+        if (tid < 6) L.misc[40 + tid] = 0;
         __syncthreads();
 
         // ------------------------------------------------ 3. projected energy
@@ -663,11 +694,6 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                 }
             }
         }
-        {
-            i64 tot;
-            block_excl_scan<BS>(used, L.misc, tot);
-            if (tid == 0) L.misc[46] = tot;
-        }
     }
 
     // ---------------------------------------------------- 4. compaction and partial statistics
@@ -683,8 +709,11 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             add128(nlo, nhi, lo, hi);
         }
     }
-    i64 total;
-    const i64 base = block_excl_scan<BS>(mine, L.misc, total);
+    // one scan gives the compaction offsets (low half) and the number of
+    // occupied slots (high half; the largest per bucket is reported)
+    i64 packed;
+    const i64 base = block_excl_scan<BS>((i64)mine | ((i64)used << 32), L.misc, packed) & 0xffffffffll;
+    const i64 total = packed & 0xffffffffll, occupied = packed >> 32;
     if (total > I.cap_t) {
         if (tid == 0) set_error(ctrl, FQE_CAP_TABLE, b);
         return;
@@ -702,7 +731,6 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             }
         }
     }
-    if (tid == 0) { L.misc[40] = 0; L.misc[41] = 0; }
     // exact wave reduction first: one LDS accumulation per wave instead of
     // one per thread on the same address
 #pragma unroll
@@ -710,7 +738,6 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         const u64 x = __shfl_down(nlo, o, 64), y = __shfl_down(nhi, o, 64);
         add128(nlo, nhi, x, y);
     }
-    __syncthreads();
     if ((tid & 63) == 0 && (nlo | nhi)) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
     __syncthreads();
     if (tid == 0) {
@@ -723,7 +750,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         pt.vproj[0] = (u64)L.misc[44];
         pt.vproj[1] = (u64)L.misc[45];
         pt.len = total;
-        pt.load = L.misc[46];
+        pt.load = occupied;
         I.part[b] = pt;
     }
     mark(4);
