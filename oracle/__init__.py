@@ -39,7 +39,7 @@ class Ham(C.Structure):
 class Params(C.Structure):
     _fields_ = [("h", Ham), ("dtau", C.c_double), ("target", C.c_double), ("zeta", C.c_double),
                 ("xi", C.c_double), ("theta", C.c_double), ("t_rel", C.c_double),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("early", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -245,10 +245,11 @@ def validate(h):
 # --------------------------------------------------------------------------
 
 def params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target=1000.0, zeta=0.08, xi=None,
-           theta=1.0, t_rel=1.0, seed=0):
+           theta=1.0, t_rel=1.0, seed=0, early=False):
     if xi is None:
         xi = zeta * zeta / 4.0
-    return Params(ham(model, M, N, t, u), dtau, target, zeta, xi, theta, t_rel, seed)
+    return Params(ham(model, M, N, t, u), dtau, target, zeta, xi, theta, t_rel, seed,
+                  1 if early else 0, 0)
 
 
 def _addr2(addrs):

@@ -38,6 +38,8 @@ typedef struct {
     orc_ham h;
     double dtau, target, zeta, xi, theta, t_rel;
     uint64_t seed;
+    int32_t early;   /* 0: late compression (default); 1: early compression (Sec. 7.1) */
+    int32_t reserved;
 } orc_params;
 
 typedef struct {
@@ -590,6 +592,29 @@ double orc_shift_update(double S, double N1, double N0, double Nt, double zeta, 
  * off-diagonal entry is always "exact" (nothing to spawn). */
 static int is_exact(double absc, double t_rel, int64_t m) { return m == 0 || absc >= t_rel * (double)m; }
 
+/* The compression rule of Eq. vec-compression for one value w with
+ * threshold theta and uniform u in [0, 1): |w| >= theta is kept, otherwise
+ * sign(w) theta when u theta < |w|, else 0. */
+static double compress1(double w, double theta, double u)
+{
+    double aw = fabs(w);
+    if (aw >= theta) return w;
+    if (aw > 0.0 && u * theta < aw) return w < 0.0 ? -theta : theta;
+    return 0.0;
+}
+
+/* Uniform of the early compression (Sec. 7.1, Eq. early-comp) of one
+ * contribution of the parent at address a in step `step`: the diagonal
+ * survivor uses tag 2, block 0; spawn attempt k uses tag 4 + (k >> 28),
+ * block k mod 2^28. */
+static double early_u(uint64_t seed, const uint64_t *a, int64_t step, int diag, int64_t k)
+{
+    uint32_t r[4];
+    if (diag) orc_draw(seed, a, (uint32_t)step, 2, 0, r);
+    else orc_draw(seed, a, (uint32_t)step, (uint32_t)(4 + (k >> 28)), (uint32_t)(k & 0x0fffffff), r);
+    return (double)r[0] * 0x1p-32;
+}
+
 /*
  * orc_step: c^(n) -> c^(n+1) for the step with index `step` (= n+1, the row
  * index of the resulting statistics).  The input table need not be sorted;
@@ -608,6 +633,13 @@ static int is_exact(double absc, double t_rel, int64_t m) { return m == 0 || abs
  *     u = r / 2^32 from the tag-1 draw of the address (Eq. vec-compression,
  *     applied after the sum: late compression, Sec. 7.1);
  *  5. statistics and the shift update.
+ *
+ * With P->early set (early compression, Eq. early-comp of Sec. 7.1, read as
+ * compressing each spawn individually), the rule of step 4 is applied
+ * instead to every contribution before the sum: to the diagonal survivor
+ * with the tag-2 draw of its address and to spawn attempt k with the draw
+ * of early_u; contributions compressed to 0 are dropped (they are not
+ * spawn events), and the sums are kept as they are.
  */
 int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64_t n,
              double shift, int64_t step, const uint64_t *ref, double yref,
@@ -648,7 +680,9 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
         orc_decode(a, M, N, occ);
         double hii = ham_diag(H, occ);
         double g = 1.0 + P->dtau * (shift - hii);
-        rec[nr].a[0] = a[0]; rec[nr].a[1] = a[1]; rec[nr].v = ci * g; nr++;
+        double sv = ci * g;
+        if (P->early) sv = compress1(sv, P->theta, early_u(P->seed, a, step, 1, 0));
+        if (sv != 0.0) { rec[nr].a[0] = a[0]; rec[nr].a[1] = a[1]; rec[nr].v = sv; nr++; }
         orc_col c;
         rc = ham_column(H, occ, &c);
         if (rc) { col_free(&c); free(rec); return rc; }
@@ -657,6 +691,8 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
             nexact++;
             for (int k = 0; k < c.n; k++) {
                 double v = (-(P->dtau * c.h[k])) * ci;
+                if (P->early) v = compress1(v, P->theta, early_u(P->seed, a, step, 0, k));
+                if (v == 0.0) continue;
                 rec[nr].a[0] = c.dest[k][0]; rec[nr].a[1] = c.dest[k][1]; rec[nr].v = v; nr++;
                 if (ev && nev < ev_cap) {
                     ev[nev].parent = i; ev[nev].attempt = k;
@@ -684,6 +720,8 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
                 int e = column_pick(H, &c, occ, r0, r1, &qnum);
                 double q = (double)qnum / (double)ni;
                 double v = ((-(P->dtau * c.h[e])) * ci) * q;
+                if (P->early) v = compress1(v, P->theta, early_u(P->seed, a, step, 0, k));
+                if (v == 0.0) continue;
                 rec[nr].a[0] = c.dest[e][0]; rec[nr].a[1] = c.dest[e][1]; rec[nr].v = v; nr++;
                 if (ev && nev < ev_cap) {
                     ev[nev].parent = i; ev[nev].attempt = k;
@@ -714,14 +752,11 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
             mg_addr[2 * nmg] = rec[s].a[0]; mg_addr[2 * nmg + 1] = rec[s].a[1]; mg_val[nmg] = w;
         }
         nmg++;
-        double aw = fabs(w), cnew = 0.0;
-        if (aw >= P->theta) {
-            cnew = w;
-        } else if (aw > 0.0) {
+        double cnew = w;
+        if (!P->early && w != 0.0 && fabs(w) < P->theta) {
             uint32_t r[4];
             orc_draw(P->seed, rec[s].a, (uint32_t)step, 1, 0, r);
-            double u = (double)r[0] * 0x1p-32;
-            if (u * P->theta < aw) cnew = w < 0.0 ? -P->theta : P->theta;
+            cnew = compress1(w, P->theta, (double)r[0] * 0x1p-32);
         }
         if (cnew != 0.0) {
             if (nout >= out_cap) { rc = ORC_ECAP; break; }

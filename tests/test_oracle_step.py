@@ -26,12 +26,14 @@ def _to_dense(orc, h, addrs, vals):
     return c
 
 
-@pytest.mark.parametrize("model,M,N,u,dtau", [(0, 5, 5, 6.0, 0.01), (1, 5, 4, 3.0, 0.01),
-                                              (0, 2, 3, 2.0, 0.02)])
-def test_step_unbiased(orc, model, M, N, u, dtau):
+@pytest.mark.parametrize("model,M,N,u,dtau,early", [(0, 5, 5, 6.0, 0.01, False), (1, 5, 4, 3.0, 0.01, False),
+                                                    (0, 2, 3, 2.0, 0.02, False), (0, 5, 5, 6.0, 0.01, True),
+                                                    (1, 5, 4, 3.0, 0.01, True)])
+def test_step_unbiased(orc, model, M, N, u, dtau, early):
     """E[T~ c] = T c (Sec. 3.2): average over seeds of the full stochastic
-    step (matrix compression + late vector compression) equals the
-    deterministic product, checked within 5 standard errors per entry."""
+    step (matrix compression + late vector compression, or early
+    compression of every contribution, Sec. 7.1) equals the deterministic
+    product, checked within 5 standard errors per entry."""
     rng = np.random.default_rng(17)
     D = orc.dimension(M, N)
     idx = rng.choice(D, size=min(D, 12), replace=False)
@@ -45,7 +47,7 @@ def test_step_unbiased(orc, model, M, N, u, dtau):
     acc2 = np.zeros(D)
     ref = addrs[0]
     for s in range(nseed):
-        P = orc.params(model, M, N, 1.0, u, dtau=dtau, target=100.0, seed=1000 + s)
+        P = orc.params(model, M, N, 1.0, u, dtau=dtau, target=100.0, seed=1000 + s, early=early)
         out = orc.step(P, addrs, vals, S, 7, ref, 1.0)
         x = _to_dense(orc, h, out["addr"], out["val"])
         acc += x
@@ -218,3 +220,26 @@ def test_sampled_pair_order_is_a_bijection(orc, M, N):
         assert set(got) == want
         with pytest.raises(Exception):
             orc.sampled_pair(h, a, len(want))
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_early_compression_contributions(orc, model):
+    """Early compression (Sec. 7.1): every spawn that survives has |v| >= theta
+    or |v| = theta exactly; the late step keeps small spawns; both steps see
+    the same parents, so early keeps at most as many spawn events."""
+    rng = np.random.default_rng(23)
+    M, N = (6, 6) if model == 0 else (6, 5)
+    D = orc.dimension(M, N)
+    idx = rng.choice(D, size=min(D, 40), replace=False)
+    addrs = [orc.unrank(int(i), M, N) for i in idx]
+    vals = rng.choice([-1, 1], len(idx)) * rng.uniform(0.5, 30.0, len(idx))
+    theta = 0.7
+    late = orc.step(orc.params(model, M, N, 1.0, 4.0, dtau=0.01, theta=theta, seed=3), addrs, vals,
+                    -1.0, 5, addrs[0], 1.0, events=True)
+    early = orc.step(orc.params(model, M, N, 1.0, 4.0, dtau=0.01, theta=theta, seed=3, early=True),
+                     addrs, vals, -1.0, 5, addrs[0], 1.0, events=True)
+    lv = np.abs(late["events"]["value"])
+    ev = np.abs(early["events"]["value"])
+    assert np.any(lv < theta)
+    assert np.all(ev >= theta)
+    assert len(ev) < len(lv) and early["stats"]["spawns"] == len(ev)
