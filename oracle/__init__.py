@@ -13,7 +13,9 @@ Contents (paper sections in brackets):
 * Philox4x32-10 counter-based draws (published definition, Salmon et al.)
 * one serial FCIQMC step and repeated steps [Sec. 3.1, 3.2, 7.1]
 * sparse-matrix and matrix-free Lanczos exact diagonalisation [Sec. 5]
-* blocking analysis, shift estimator, ratio of means [Sec. 4] (``stats``)
+* replica overlaps c_A . c_B [Sec. 4.3]
+* blocking analysis, shift estimator, ratio of means, variational energy
+  [Sec. 4] (``stats``)
 
 Parity status of every function is listed in the design doc; every function here
 is pinned by a ``-m "not gpu"`` test against the paper's printed values,
@@ -321,6 +323,39 @@ def run(P, addrs, vals, shift, first_step, nsteps, ref, yref, cap=None):
         for f in STATS_FIELDS:
             arr[f][k] = getattr(stats[k], f)
     return arr, oa[:on.value].copy(), ov[:on.value].copy()
+
+
+# --------------------------------------------------------------------------
+# Replica overlaps [Sec. 4.3]
+# --------------------------------------------------------------------------
+
+def replica_pairs(R):
+    """The pairs (A, B), A < B, of R replicas in the order A = 0.., then B."""
+    return [(a, b) for a in range(R) for b in range(a + 1, R)]
+
+
+def _keys(addrs):
+    a = np.ascontiguousarray(np.asarray(addrs, dtype=np.uint64).reshape(len(addrs), -1))
+    return a.view(np.dtype((np.void, 8 * a.shape[1]))).ravel()
+
+
+def overlap(addrs_a, vals_a, addrs_b, vals_b):
+    """Dot product c_A . c_B of two sparse vectors [Sec. 4.3, Eq.
+    RayleighQuotientReplica, denominator term].
+
+    Addresses present in only one of the vectors contribute nothing.  Each
+    product of two amplitudes is rounded to double; the products are summed
+    exactly and rounded once (math.fsum).  Address rows must be unique
+    within each vector and use the same number of words.
+    """
+    import math
+    ka, kb = _keys(addrs_a), _keys(addrs_b)
+    if len(np.unique(ka)) != len(ka) or len(np.unique(kb)) != len(kb):
+        raise ValueError("overlap: duplicate address")
+    _, ia, ib = np.intersect1d(ka, kb, assume_unique=True, return_indices=True)
+    va = np.asarray(vals_a, dtype=np.float64)[ia]
+    vb = np.asarray(vals_b, dtype=np.float64)[ib]
+    return math.fsum((va * vb).tolist())
 
 
 # --------------------------------------------------------------------------

@@ -13,6 +13,8 @@
 * shift estimator = blocked mean of the shift after `skip` steps (Sec. 4.2).
 * ratio of means with linear error propagation using the blocked variances
   and covariance at the common blocking level (Sec. 4.2, reading).
+* variational energy from replica shifts and overlaps (Sec. 4.3).  Reading:
+  the shift and the overlap of the same step are paired.
 """
 from dataclasses import dataclass
 
@@ -104,3 +106,28 @@ def ratio_of_means(num, den, skip=0):
 
 def projected_energy(hproj, vproj, skip=0):
     return ratio_of_means(hproj, vproj, skip)
+
+
+def variational_energy(shifts, overlaps, skip=0):
+    """Variational energy from R replicas [Sec. 4.3, Eq.
+    RayleighQuotientReplica with the Hamiltonian as the observable].
+
+    shifts: (R, n) shift time series S_A^(n); overlaps: (P, n) time series
+    c_A^(n) . c_B^(n) of the P = R(R-1)/2 pairs in the order A = 0.., then B.
+    The numerator of pair (A, B) at step n is (S_A + S_B)/2 times its overlap
+    at the same step; numerators and denominators are summed over pairs and
+    the ratio of their means is taken with blocking.
+    """
+    S = np.asarray(shifts, dtype=np.float64)
+    O = np.asarray(overlaps, dtype=np.float64)
+    R = S.shape[0]
+    pairs = [(a, b) for a in range(R) for b in range(a + 1, R)]
+    if O.shape[0] != len(pairs):
+        raise ValueError("variational_energy: need one overlap series per replica pair")
+    num = np.zeros(S.shape[1])
+    den = np.zeros(S.shape[1])
+    for (a, b), o in zip(pairs, O):
+        num += 0.5 * (S[a] + S[b]) * o
+        den += o
+    return ratio_of_means(num, den, skip)
+
