@@ -182,6 +182,54 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
     return out
 
 
+def bench_replicas(fq, torch, wl, cfg, warmup=1500, steps=300):
+    """Two replicas of the momentum-space workload (seeds differ) in one
+    batch with the overlap c_A . c_B computed after every step on the
+    device (Sec. 4.3).  The same replicas then run the same number of steps
+    without overlaps; the difference per step is the cost of the join."""
+    specs = [dict(model=cfg["model"], M=cfg["M"], N=cfg["N"], t=cfg["t"], u=cfg["u"], dtau=cfg["dtau"],
+                  target_walkers=cfg["target"], seed=sd, addr_words=cfg["W"], threshold=cfg["theta"],
+                  table_capacity=wl["table_capacity"], spawn_capacity=wl["spawn_capacity"],
+                  buckets=wl["buckets"], lds_slots=wl["lds_slots"], block=wl["block"],
+                  spawn_block=wl["spawn_block"]) for sd in (cfg["seed"], cfg["seed"] + 100)]
+    b = fq.Batch(specs)
+    a = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), cfg["W"])
+    for i in range(2):
+        b.instance(i).set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup:
+        k = min(500, warmup - done)
+        b.run(k)
+        done += k
+        log(f"[bench] replica warmup {done}/{warmup} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st, ov, inexact = b.run_replicas(steps)
+    torch.cuda.synchronize()
+    wall_o = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    st2 = b.run(steps)
+    torch.cuda.synchronize()
+    wall_n = time.perf_counter() - t2
+    b.close()
+    rec = 8 * cfg["W"] + 8
+    join_bytes = float(rec * (st["len"][0] + st["len"][1]).astype(np.float64).mean())
+    over_ms = (wall_o - wall_n) / steps * 1e3
+    out = dict(workload=f"2 replicas of {wl['name']} (seeds {cfg['seed']}, {cfg['seed'] + 100})",
+               replicas=2, warmup=warmup, steps=steps,
+               walker_steps_per_s=float(st["norm"].sum()) / wall_o, ms_per_step=wall_o / steps * 1e3,
+               ms_per_step_without_overlaps=wall_n / steps * 1e3, overlap_ms_per_step=over_ms,
+               overlap_algorithmic_bytes_per_step=join_bytes,
+               overlap_GBs_from_difference=join_bytes / max(over_ms, 1e-6) / 1e6,
+               last_overlap=float(ov[-1, 0]), inexact=bool(inexact),
+               mean_walkers=[float(st["norm"][0].mean()), float(st["norm"][1].mean())])
+    log(f"[bench] replicas {out['walker_steps_per_s']:.4g} walker-steps/s, {out['ms_per_step']:.3f} ms/step "
+        f"({out['ms_per_step_without_overlaps']:.3f} without overlaps)")
+    del st2
+    return out
+
+
 def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
     """The first n_req requests of the Poisson stream (lambda = 50/s, M = N in
     6..20, u in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7]) served
@@ -235,6 +283,47 @@ def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
     return out
 
 
+def blocked_error(x):
+    """Standard error of the mean of a correlated series by blocking
+    (Flyvbjerg-Petersen): the largest blocked estimate over levels that keep
+    at least 32 blocks."""
+    x = np.asarray(x, dtype=np.float64)
+    best = 0.0
+    while len(x) >= 32:
+        best = max(best, math.sqrt(np.var(x) / (len(x) - 1)))
+        n = len(x) // 2
+        x = 0.5 * (x[:2 * n:2] + x[1:2 * n:2])
+    return best
+
+
+def compression_study(fq, torch, steps=20000, skip=5000):
+    """Statistical efficiency f = 1 / (sigma^2 Omega t) of the shift (Sec. 7.1)
+    for late and early compression on the real-space 12/12 ring (u = 6,
+    dtau = 1e-3, N_t = 1e4): sigma = blocked error of the mean shift, Omega =
+    steps after `skip`, t = GPU time per step from HIP events."""
+    out = {}
+    for name, flag in (("late", 0), ("early", fq.FLAG_EARLY_COMPRESSION)):
+        s = fq.Solver(fq.REAL1D, 12, 12, u=6.0, dtau=1e-3, target_walkers=1e4, seed=7, flags=flag,
+                      table_capacity=40000, spawn_capacity=200000)
+        a = fq.start_address(fq.REAL1D, 12, 12)
+        s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+        s.run(skip)
+        s.set_timing(True)
+        s.kernel_time(reset=True)
+        st = s.run(steps)
+        kms, nl = s.kernel_time()
+        s.close()
+        t = sum(kms.values()) / 1e3 / max(nl, 1)
+        sig = blocked_error(st["shift"])
+        out[name] = dict(mean_shift=float(st["shift"].mean()), sigma=sig, steps=steps, s_per_step=t,
+                         f=1.0 / (sig * sig * steps * t), mean_len=float(st["len"].mean()),
+                         mean_spawns=float(st["spawns"].mean()))
+        log(f"[bench] compression {name}: shift {out[name]['mean_shift']:.5f} +- {sig:.5f}, "
+            f"{t * 1e3:.4f} ms/step, f {out[name]['f']:.4g}")
+    return dict(workload="real-space 1D Bose-Hubbard ring M = N = 12, u = 6, dtau = 1e-3, N_t = 1e4",
+                **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,9 +339,12 @@ def main():
     ap.add_argument("--spawn-block", type=int, default=None)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurement")
+    ap.add_argument("--no-replicas", action="store_true", help="skip the replica-overlap measurement")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-warmup", type=int, default=1500)
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--compression-study", action="store_true",
+                    help="only compare late and early compression by statistical efficiency")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a streaming negation over this many MiB (reads and writes "
                          "that many bytes): the reference kernel for HBM byte counters")
@@ -266,6 +358,10 @@ def main():
     import torch
     import paper_2601_19505_amd as fq
 
+    if args.compression_study:
+        torch.cuda.set_device(0)
+        print(json.dumps({"compression_study": compression_study(fq, torch)}), flush=True)
+        return
     wl = dict(WORKLOADS[args.workload])
     for k_arg, k_wl in (("buckets", "buckets"), ("slots", "lds_slots"), ("block", "block"),
                         ("spawn_block", "spawn_block")):
@@ -380,6 +476,9 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if not args.no_replicas and args.workload == "c3":
+        out["replicas"] = bench_replicas(fq, torch, wl, cfg, warmup=args.batch_warmup)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = bench_batched(fq, torch, warmup=args.batch_warmup, steps=args.batch_steps)
         torch.cuda.empty_cache()

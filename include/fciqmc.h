@@ -83,6 +83,13 @@ typedef struct {
 #define FQ_FLAG_DUMP_SPAWNS 1   /* record every spawn event (parity testing)      */
 #define FQ_FLAG_DUMP_MERGED 2   /* record every merged pre-compression amplitude  */
 #define FQ_FLAG_PHASE_TIMING 4  /* accumulate per-phase timers (diagnostics)      */
+/* Early compression (Sec. 7.1, Eq. early-comp): the compression rule of Eq.
+ * vec-compression is applied to every contribution before annihilation --
+ * the diagonal survivor (draw tag 2, block 0, keyed by its address) and each
+ * spawn attempt k (tag 4 + (k >> 28), block k mod 2^28, keyed by the
+ * parent) -- instead of to the sums (late compression, the default).
+ * Contributions compressed to 0 are not spawn events. */
+#define FQ_FLAG_EARLY_COMPRESSION 32
 /* Sampled dumps: with FQ_FLAG_DUMP_SAMPLE(k), k in 1..20, the dumps keep only
  * the spawn events whose destination, and the merged amplitudes whose
  * address, fall in a fixed sample of about 2^-k of all addresses (bits
@@ -212,7 +219,8 @@ int fq_autotune(fq_handle *src, const fq_layout *candidates, int32_t n, int32_t 
  * from a map), with per-instance tables, shifts and statistics.  Instances
  * may differ in Hamiltonian (M, N, t, u), parameters and capacities; they
  * must share the model kind (real space, momentum space with M <= 16 or
- * M <= 32), addr_words, lds_slots, block and spawn_block.  Every instance
+ * M <= 32), the compression style (FQ_FLAG_EARLY_COMPRESSION set or not),
+ * addr_words, lds_slots, block and spawn_block.  Every instance
  * produces the same results as it would alone.
  *
  * fq_batch_workspace_size: bytes of the single workspace for the batch
@@ -235,6 +243,45 @@ int fq_batch_instance(fq_batch *b, int32_t i, fq_handle **out);
 int fq_batch_run(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *stream);
 int32_t fq_batch_failed(const fq_batch *b);
 int fq_batch_destroy(fq_batch *b);
+/* Description of the last failure of a batch call (b may be NULL for a
+ * failed fq_batch_create); instance failures are also reported by
+ * fq_last_error() of the instance that fq_batch_failed() names. */
+const char *fq_batch_last_error(const fq_batch *b);
+
+/* ------------------------------------------------------------------------
+ * Replicas (Sec. 4.3, Eq. RayleighQuotientReplica): a batch of R = 2 ..
+ * FQ_MAX_REPLICAS statistically independent runs of one Hamiltonian
+ * (identical fq_hamiltonian, addr_words, buckets and lds_slots; normally
+ * only the seed differs), stepped together.  After every step the overlap
+ * c_A . c_B of each pair A < B is computed on the device: the sum over the
+ * addresses present in both tables of the product of the two amplitudes,
+ * each product rounded to double, the products summed exactly (192-bit
+ * fixed point with 96 fractional bits) and rounded once to the nearest
+ * double.  The result equals the exactly rounded sum when every product is
+ * a multiple of 2^-96 (always when |c_A c_B| >= 2^-43); otherwise that
+ * product is rounded half-even to a multiple of 2^-96 and *inexact is set.
+ * The variational energy of Sec. 4.3 is the ratio of the means of
+ * (S_A + S_B)/2 c_A.c_B and c_A.c_B summed over pairs, with the shifts of
+ * the statistics rows of the same steps.
+ *
+ * fq_batch_replica_scratch_size: bytes of device scratch (caller owned,
+ * 256-byte aligned) for fq_batch_run_replicas.  FQ_EINVAL when the batch is
+ * not a valid replica set.
+ * fq_batch_run_replicas: as fq_batch_run (stats may be NULL), and
+ * overlaps (host, required) receives n_steps rows of P = R(R-1)/2 doubles,
+ * row k = the overlaps after step k, pairs in the order (0,1), (0,2), ..,
+ * (0,R-1), (1,2), ...  All replicas must hold a state at the same step.  A
+ * pair whose two replicas are not both error-free at the same step reads
+ * NaN.  Errors: FQ_ECAPACITY when a bucket of a table does not fit the
+ * lds_slots hash of the join, FQ_EDIVERGED when a product has magnitude
+ * 2^95 or more; a failing instance is reported as by fq_batch_run.  The
+ * rows of the steps completed before a failure are filled.  inexact (may
+ * be NULL) is set to 1 when some product was rounded (see above), else 0.
+ * ------------------------------------------------------------------------ */
+#define FQ_MAX_REPLICAS 8
+int fq_batch_replica_scratch_size(fq_batch *b, size_t *bytes);
+int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, void *scratch,
+                          size_t scratch_bytes, int32_t *inexact, void *stream);
 
 /* ------------------------------------------------------------------------
  * Server: continuous batching of FCIQMC solves on one GPU.
@@ -255,8 +302,9 @@ int fq_batch_destroy(fq_batch *b);
  * fq_server_poll reports a request's state, its last statistics row and the
  * means of shift, y.Hc and y.c over the steps after the first half.  All
  * requests of one server share the model, addr_words, lds_slots, block and
- * spawn_block of its configuration (momentum space: M <= 16).  Not thread
- * safe.
+ * spawn_block of its configuration (momentum space: M <= 16) and use late
+ * compression (a request with FQ_FLAG_EARLY_COMPRESSION is refused with
+ * FQ_EINVAL).  Not thread safe.
  * ------------------------------------------------------------------------ */
 typedef struct fq_server fq_server;
 typedef struct {

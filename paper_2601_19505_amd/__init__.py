@@ -21,6 +21,7 @@ MOM1D = 1
 FLAG_DUMP_SPAWNS = 1
 FLAG_DUMP_MERGED = 2
 FLAG_PHASE_TIMING = 4
+FLAG_EARLY_COMPRESSION = 32
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ENOMEM", -5: "EBUSY",
           -6: "EDIVERGED", -7: "ENOTFOUND"}
@@ -122,6 +123,10 @@ def lib():
             "fq_batch_instance": (C.c_int, [vp, C.c_int32, P(vp)]),
             "fq_batch_run": (C.c_int, [vp, C.c_int64, vp, vp]),
             "fq_batch_failed": (C.c_int32, [vp]),
+            "fq_batch_last_error": (C.c_char_p, [vp]),
+            "fq_batch_replica_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+            "fq_batch_run_replicas": (C.c_int, [vp, C.c_int64, vp, vp, vp, C.c_size_t,
+                                                C.POINTER(C.c_int32), vp]),
             "fq_batch_destroy": (C.c_int, [vp]),
             "fq_server_create": (C.c_int, [P(ServerConfig), vp, C.c_size_t, P(vp)]),
             "fq_server_submit": (C.c_int, [vp, P(Hamiltonian), P(Params), P(Layout), u64p, C.c_double,
@@ -414,6 +419,7 @@ class Batch:
         if rc:
             raise FqError(rc, f"fq_batch_create: {lib().fq_last_error(None).decode()}")
         self.b = b
+        self._ov = None
         self._inst = []
         for i in range(n):
             h = C.c_void_p()
@@ -440,6 +446,35 @@ class Batch:
             err.instance = i
             raise err
         return out
+
+    def run_replicas(self, n_steps):
+        """Advance every instance as replicas of one Hamiltonian (Sec. 4.3)
+        and compute the overlap c_A . c_B of every pair A < B after every
+        step on the device.  Returns (stats of shape (n, n_steps), overlaps
+        of shape (n_steps, P) with pairs (0,1), (0,2), .., (1,2), ..,
+        inexact flag)."""
+        import torch
+        if self._ov is None:
+            nb = C.c_size_t(0)
+            rc = lib().fq_batch_replica_scratch_size(self.b, C.byref(nb))
+            if rc:
+                raise FqError(rc, f"fq_batch_replica_scratch_size: {lib().fq_batch_last_error(self.b).decode()}")
+            self._ov = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        P = self.n * (self.n - 1) // 2
+        out = np.zeros((self.n, n_steps), STATS_DTYPE)
+        ovl = np.zeros((n_steps, P), np.float64)
+        inexact = C.c_int32(0)
+        rc = lib().fq_batch_run_replicas(self.b, n_steps, C.c_void_p(out.ctypes.data),
+                                         C.c_void_p(ovl.ctypes.data), C.c_void_p(self._ov.data_ptr()),
+                                         self._ov.numel(), C.byref(inexact), _stream())
+        if rc:
+            i = lib().fq_batch_failed(self.b)
+            msg = (lib().fq_last_error(self._inst[i].h).decode() if i >= 0
+                   else lib().fq_batch_last_error(self.b).decode())
+            err = FqError(rc, f"fq_batch_run_replicas: {msg}")
+            err.stats, err.overlaps, err.instance = out, ovl, i
+            raise err
+        return out, ovl, bool(inexact.value)
 
     def close(self):
         if getattr(self, "b", None):

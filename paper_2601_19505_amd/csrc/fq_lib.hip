@@ -23,6 +23,7 @@
 #include <unordered_map>
 
 #include "fciqmc.h"
+#include "fq_overlap.hpp"
 #include "fq_step.hpp"
 
 using namespace fq;
@@ -45,22 +46,24 @@ __device__ __forceinline__ const Inst &locate(const Inst *const *insts, const u3
     return *insts[0];
 }
 
-template <int W, int MODEL, int BS>
+// EARLY: early compression (separate kernels, so the late-compression
+// kernels carry none of its code and registers)
+template <int W, int MODEL, int BS, bool EARLY>
 __global__ __launch_bounds__(BS) void k_merge(const Inst *const *insts, const u32 *map)
 {
     extern __shared__ __align__(16) char smem[];
     int b;
     const Inst &I = locate(insts, map, b);
-    merge_bucket<W, MODEL, BS>(I, b, smem);
+    merge_bucket<W, MODEL, BS, EARLY>(I, b, smem);
 }
 
-template <int W, int MODEL, int BS>
+template <int W, int MODEL, int BS, bool EARLY>
 __global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u32 *map, int mode)
 {
     extern __shared__ __align__(16) char smem[];
     int b;
     const Inst &I = locate(insts, map, b);
-    spawn_bucket<W, MODEL, BS>(I, b, mode, smem);
+    spawn_bucket<W, MODEL, BS, EARLY>(I, b, mode, smem);
 }
 
 // one workgroup per instance
@@ -116,6 +119,20 @@ __global__ void k_gather_ctrl(const Inst *const *insts, int n, Ctrl *out)
         u32 *dst = (u32 *)(out + i);
         for (int k = threadIdx.x; k < (int)(sizeof(Ctrl) / 4); k += blockDim.x) dst[k] = src[k];
     }
+}
+
+// replica overlaps: workgroup A * B + b joins bucket b of replica A with the
+// same bucket of every replica after A; then one workgroup sums the buckets
+constexpr int OV_BS = 256;
+template <int W> __global__ __launch_bounds__(OV_BS) void k_overlap(Overlap O)
+{
+    extern __shared__ __align__(16) char smem[];
+    overlap_bucket<W, OV_BS>(O, (int)blockIdx.x / O.B, (int)blockIdx.x % O.B, smem);
+}
+__global__ __launch_bounds__(1024) void k_overlap_fin(Overlap O) { overlap_finalize<1024>(O); }
+__global__ void k_fill_i32(int *p, int n, int v)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
 // insert host-staged entries into table[parity] and accumulate the norm
@@ -228,26 +245,37 @@ constexpr i64 RING = 4096;
 constexpr int NEV = 5;  // timing events per step: merge | spawn | partition | finalize
 constexpr int REFCAP = 1 << 15;
 
-template <int W, int MODEL>
-const void *pick_kernel(int bs, bool spawn)
+template <int W, int MODEL, bool E>
+const void *pick_bs(int bs, bool spawn)
 {
     switch (bs) {
-    case 256: return spawn ? (const void *)k_spawn<W, MODEL, 256> : (const void *)k_merge<W, MODEL, 256>;
-    case 512: return spawn ? (const void *)k_spawn<W, MODEL, 512> : (const void *)k_merge<W, MODEL, 512>;
-    default: return spawn ? (const void *)k_spawn<W, MODEL, 1024> : (const void *)k_merge<W, MODEL, 1024>;
+    case 256: return spawn ? (const void *)k_spawn<W, MODEL, 256, E> : (const void *)k_merge<W, MODEL, 256, E>;
+    case 512: return spawn ? (const void *)k_spawn<W, MODEL, 512, E> : (const void *)k_merge<W, MODEL, 512, E>;
+    default: return spawn ? (const void *)k_spawn<W, MODEL, 1024, E> : (const void *)k_merge<W, MODEL, 1024, E>;
     }
 }
+template <int W, int MODEL>
+const void *pick_kernel(int bs, bool spawn, bool early)
+{
+    return early ? pick_bs<W, MODEL, true>(bs, spawn) : pick_bs<W, MODEL, false>(bs, spawn);
+}
 
-// kernel variant: 0 real space, 1 momentum space with M <= 16, 2 momentum with M <= 32
-int variant(int model, int M) { return model == 0 ? 0 : (M <= 16 ? 1 : 2); }
+// kernel variant: 0 real space, 1 momentum space with M <= 16, 2 momentum
+// with M <= 32; plus 3 with early compression
+int variant(int model, int M, int flags)
+{
+    return (model == 0 ? 0 : (M <= 16 ? 1 : 2)) + ((flags & FQ_FLAG_EARLY_COMPRESSION) ? 3 : 0);
+}
 
 const void *step_kernel(int W, int var, int bs, bool spawn)
 {
+    const bool e = var >= 3;
+    const int m = var % 3;
     if (W == 1)
-        return var == 0 ? pick_kernel<1, 0>(bs, spawn) : var == 1 ? pick_kernel<1, 1>(bs, spawn)
-                                                                   : pick_kernel<1, 2>(bs, spawn);
-    return var == 0 ? pick_kernel<2, 0>(bs, spawn) : var == 1 ? pick_kernel<2, 1>(bs, spawn)
-                                                               : pick_kernel<2, 2>(bs, spawn);
+        return m == 0 ? pick_kernel<1, 0>(bs, spawn, e) : m == 1 ? pick_kernel<1, 1>(bs, spawn, e)
+                                                               : pick_kernel<1, 2>(bs, spawn, e);
+    return m == 0 ? pick_kernel<2, 0>(bs, spawn, e) : m == 1 ? pick_kernel<2, 1>(bs, spawn, e)
+                                                           : pick_kernel<2, 2>(bs, spawn, e);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -676,8 +704,8 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
-    const void *km = step_kernel(R.W, variant(h->model, h->M), R.block, false);
-    const void *ks = step_kernel(R.W, variant(h->model, h->M), R.spawn_block, true);
+    const void *km = step_kernel(R.W, variant(h->model, h->M, p->flags), R.block, false);
+    const void *ks = step_kernel(R.W, variant(h->model, h->M, p->flags), R.spawn_block, true);
     hipError_t e = hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
@@ -694,7 +722,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
     Exec &X = q->X;
     X.W = R.W;
-    X.var = variant(h->model, h->M);
+    X.var = variant(h->model, h->M, p->flags);
     X.block = R.block;
     X.spawn_block = R.spawn_block;
     X.lds_m = lds_bytes(R.W, R.slots);
@@ -1188,12 +1216,41 @@ int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &e
     return FQ_OK;
 }
 
+// Replica overlaps computed after every step of a group (all instances of
+// the group are the replicas).  `out` receives rows of P doubles (advanced).
+struct OvRun {
+    Overlap O;
+    int W = 1;
+    size_t lds = 0;
+    double *out = nullptr;
+};
+
+size_t overlap_lds_bytes(int W, int slots)
+{
+    return (size_t)slots * (W == 2 ? 28 : 16) + sizeof(Fx3) * (OV_BS / 64);
+}
+
+hipError_t launch_overlap(const OvRun &ov, hipStream_t s)
+{
+    const void *kf = ov.W == 1 ? (const void *)k_overlap<1> : (const void *)k_overlap<2>;
+    Overlap O = ov.O;
+    void *args[] = {(void *)&O};
+    hipError_t e = hipLaunchKernel(kf, dim3((O.R - 1) * O.B), dim3(OV_BS), args, ov.lds, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_overlap_fin, dim3(1), dim3(1024), 0, s, O);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
 // Runs `steps` steps of every instance of G (an instance that has failed or
 // reached its stop step does no work).  When rows is given, the statistics
 // rows of grid position j are appended at (*rows)[j] (advanced), if not
-// null.  Returns the status of the first failing instance (grid position in
-// *failed) after the chunk in which it failed.
-int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStream_t s, int *failed, std::string &err)
+// null.  With ov, the replica overlaps of every step are computed and their
+// rows appended at ov->out.  Returns the status of the first failing
+// instance (grid position in *failed) after the chunk in which it failed.
+int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStream_t s, int *failed, std::string &err,
+                OvRun *ov = nullptr)
 {
     const Exec &X = G.X;
     i64 launched = 0;
@@ -1202,7 +1259,10 @@ int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStre
         const i64 chunk = std::min<i64>(RING, steps - launched);
         hipLaunchKernelGGL(k_begin_chunk, dim3(1), dim3(256), 0, s, X.insts, X.n);
         hipError_t e = hipGetLastError();
-        for (i64 k = 0; k < chunk && e == hipSuccess; k++) e = exec_step(X, s, nullptr);
+        for (i64 k = 0; k < chunk && e == hipSuccess; k++) {
+            e = exec_step(X, s, nullptr);
+            if (e == hipSuccess && ov) e = launch_overlap(*ov, s);
+        }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_gather_ctrl, dim3(std::min(X.n, 1024)), dim3(64), 0, s, X.insts, X.n, G.d_ctrl_out);
             e = hipGetLastError();
@@ -1210,6 +1270,15 @@ int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStre
         if (e == hipSuccess) e = hipMemcpyAsync(G.ctrl.data(), G.d_ctrl_out, sizeof(Ctrl) * X.n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { err = std::string("group step: ") + hipGetErrorString(e); return FQ_EHIP; }
+        if (ov) {
+            i64 done = chunk;
+            for (int j = 0; j < X.n; j++) done = std::min<i64>(done, G.ctrl[j].step - G.h[j]->step);
+            if (done > 0) {
+                e = hipMemcpy(ov->out, ov->O.ring, sizeof(double) * ov->O.P * done, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) { err = std::string("overlap rows: ") + hipGetErrorString(e); return FQ_EHIP; }
+                ov->out += ov->O.P * done;
+            }
+        }
         for (int j = 0; j < X.n; j++) {
             fq_handle *q = G.h[j];
             const Ctrl &c = G.ctrl[j];
@@ -1261,10 +1330,12 @@ int batch_plan(int n, const fq_hamiltonian *h, const fq_params *p, const fq_layo
         int rc = resolve(&h[i], &p[i], &lay[i], R, L, err);
         if (rc) { err = "batch instance " + std::to_string(i) + ": " + err; return rc; }
         if (i == 0) R0 = R;
-        if (R.W != R0.W || variant(h[i].model, h[i].M) != variant(h[0].model, h[0].M) || R.block != R0.block ||
+        if (R.W != R0.W || variant(h[i].model, h[i].M, p[i].flags) != variant(h[0].model, h[0].M, p[0].flags) ||
+            R.block != R0.block ||
             R.spawn_block != R0.spawn_block || R.slots != R0.slots) {
             err = "batch instance " + std::to_string(i) +
-                  ": instances must share the model kind, addr_words, lds_slots, block and spawn_block";
+                  ": instances must share the model kind, the compression style (early or late), addr_words, "
+                  "lds_slots, block and spawn_block";
             return FQ_EINVAL;
         }
         sz[i] = align256(R.total);
@@ -1359,6 +1430,118 @@ int fq_batch_run(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *strea
             if (b->pos[i] == failed) b->failed = i;
     return rc;
 }
+
+// The batch as a set of replicas: at least 2 and at most FQ_MAX_REPLICAS
+// instances of one Hamiltonian with one bucket count.
+static int replica_check(fq_batch *b, std::string &err)
+{
+    const int n = (int)b->inst.size();
+    if (n < 2 || n > FQ_MAX_REPLICAS) {
+        err = "replicas: need 2 to " + std::to_string(FQ_MAX_REPLICAS) + " instances";
+        return FQ_EINVAL;
+    }
+    const fq_handle *q0 = b->inst[0];
+    for (int i = 1; i < n; i++) {
+        const fq_handle *q = b->inst[i];
+        if (q->h.model != q0->h.model || q->h.M != q0->h.M || q->h.N != q0->h.N ||
+            memcmp(&q->h.t, &q0->h.t, sizeof(double)) || memcmp(&q->h.u, &q0->h.u, sizeof(double)) ||
+            q->R.B != q0->R.B || q->R.W != q0->R.W || q->R.slots != q0->R.slots) {
+            err = "replicas: instance " + std::to_string(i) +
+                  " differs from instance 0 in its Hamiltonian, addr_words, buckets or lds_slots";
+            return FQ_EINVAL;
+        }
+    }
+    return FQ_OK;
+}
+
+struct OvScratch {
+    size_t rep, part, ring, flags, total;
+};
+
+static OvScratch ov_scratch(int R, int B)
+{
+    const int P = R * (R - 1) / 2;
+    OvScratch o;
+    o.rep = 0;
+    o.part = align256(sizeof(Inst *) * R);
+    o.ring = o.part + align256(sizeof(Fx3) * (size_t)B * P);
+    o.flags = o.ring + align256(sizeof(double) * (size_t)RING * P);
+    o.total = o.flags + 256;
+    return o;
+}
+
+int fq_batch_replica_scratch_size(fq_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return FQ_EINVAL;
+    int rc = replica_check(b, b->err);
+    if (rc) return rc;
+    *bytes = ov_scratch((int)b->inst.size(), b->inst[0]->R.B).total;
+    return FQ_OK;
+}
+
+int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, void *scratch,
+                          size_t scratch_bytes, int32_t *inexact, void *stream)
+{
+    if (!b || n_steps < 0 || !overlaps) return FQ_EINVAL;
+    int rc = replica_check(b, b->err);
+    if (rc) return rc;
+    const int R = (int)b->inst.size(), P = R * (R - 1) / 2;
+    const fq_handle *q0 = b->inst[0];
+    const OvScratch lay = ov_scratch(R, q0->R.B);
+    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < lay.total) {
+        b->err = "replicas: scratch must be 256-byte aligned and at least fq_batch_replica_scratch_size bytes";
+        return FQ_EINVAL;
+    }
+    for (int i = 0; i < R; i++) {
+        if (!b->inst[i]->have_state) { b->err = "replicas: instance " + std::to_string(i) + " has no state"; return FQ_EINVAL; }
+        if (b->inst[i]->step != q0->step) { b->err = "replicas: instances are at different steps"; return FQ_EINVAL; }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *sc = (char *)scratch;
+    std::vector<const Inst *> rep(R);
+    for (int i = 0; i < R; i++) rep[i] = b->inst[i]->d_inst;
+    OvRun ov;
+    ov.W = q0->R.W;
+    ov.lds = overlap_lds_bytes(ov.W, q0->R.slots);
+    ov.out = overlaps;
+    ov.O.rep = (const Inst *const *)(sc + lay.rep);
+    ov.O.R = R;
+    ov.O.P = P;
+    ov.O.B = q0->R.B;
+    ov.O.part = (Fx3 *)(sc + lay.part);
+    ov.O.ring = (double *)(sc + lay.ring);
+    ov.O.ring_cap = RING;
+    ov.O.flags = (int *)(sc + lay.flags);
+    hipError_t e = ensure_lds(ov.W == 1 ? (const void *)k_overlap<1> : (const void *)k_overlap<2>, ov.lds);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)ov.O.rep, rep.data(), sizeof(Inst *) * R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, ov.O.flags, 4, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { b->err = std::string("replicas: ") + hipGetErrorString(e); return FQ_EHIP; }
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(256), 0, s, b->G.X.insts, R, (i64)n_steps);
+    std::vector<fq_step_stats *> rows(R, nullptr);
+    if (stats)
+        for (int i = 0; i < R; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
+    int failed = -1;
+    b->failed = -1;
+    rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err, &ov);
+    if (failed >= 0)
+        for (int i = 0; i < R; i++)
+            if (b->pos[i] == failed) b->failed = i;
+    int fl[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(fl, ov.O.flags, sizeof(fl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { b->err = std::string("replicas: ") + hipGetErrorString(e); return FQ_EHIP; }
+    if (inexact) *inexact = fl[1];
+    if (rc) return rc;
+    if (fl[0]) { b->err = "replicas: a table bucket does not fit the overlap hash (lds_slots)"; return FQ_ECAPACITY; }
+    if (fl[2]) { b->err = "replicas: an amplitude product is out of the overlap range"; return FQ_EDIVERGED; }
+    return FQ_OK;
+}
+
+const char *fq_batch_last_error(const fq_batch *b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 int32_t fq_batch_failed(const fq_batch *b) { return b ? b->failed : -1; }
 
@@ -1489,6 +1672,10 @@ int fq_server_submit(fq_server *sv, const fq_hamiltonian *h, const fq_params *p,
         return FQ_EINVAL;
     if (h->model != sv->cfg.model || p->addr_words != sv->cfg.addr_words) {
         sv->err = "submit: model or addr_words differ from the server's";
+        return FQ_EINVAL;
+    }
+    if (p->flags & FQ_FLAG_EARLY_COMPRESSION) {
+        sv->err = "submit: the server runs late compression only";
         return FQ_EINVAL;
     }
     Req r;

@@ -125,6 +125,18 @@ __device__ __forceinline__ bool dump_keeps(int flags, u64 h)
     return k == 0 || ((h >> 24) & ((1ull << k) - 1)) == 0;
 }
 
+// the compression rule of Eq. vec-compression for one value: |w| >= theta
+// kept, otherwise sign(w) theta when u theta < |w| (u = r 2^-32), else 0
+__device__ __forceinline__ double compress1(double w, double theta, u32 r)
+{
+    const double aw = fabs(w);
+    if (aw >= theta) return w;
+    const double u = (double)r * 0x1p-32;
+    return (aw > 0.0 && u * theta < aw) ? (w < 0.0 ? -theta : theta) : 0.0;
+}
+
+constexpr int FLAG_EARLY = 32;  // early compression (FQ_FLAG_EARLY_COMPRESSION)
+
 __device__ __forceinline__ int halted(Ctrl *c)
 {
     const int e = __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -325,7 +337,9 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
 // two-pass partition a group is a coarse group of buckets and the run lies in
 // the coarse sub-slab of the producing bucket (bucket mod 64); otherwise a group
 // is a bucket and the run lies in its slab.
-template <int W> struct SpawnOut {
+// COUNT: also count the records emitted (early compression drops records, so
+// the spawn count is not the attempt count)
+template <int W, bool COUNT> struct SpawnOut {
     typedef typename AddrOf<W>::T T;
     const Inst &I;
     const Lds &L;
@@ -354,6 +368,7 @@ template <int W> struct SpawnOut {
             const int cg = gcnt()[tid];
             int *cn = I.two_pass ? &I.coarse_n[(tid << I.log2SUB) + sub] : &I.slab_n[out_par][tid];
             gbase()[tid] = cg ? (i64)atomicAdd(cn, cg) : 0;
+            if (COUNT && cg) atomicAdd((unsigned long long *)&L.misc[60], (unsigned long long)cg);
         }
         __syncthreads();
     }
@@ -396,7 +411,7 @@ template <int W> struct SpawnOut {
 #ifndef FQ_SPAWN_NR
 #define FQ_SPAWN_NR 4
 #endif
-template <int W, int MODEL, int BS>
+template <int W, int MODEL, int BS, bool EARLY>
 __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const int b, const int par,
                                            const u32 spawn_step, const int w0_, const int nS, const u32 *info,
                                            const u32 *perm, const i64 A, const unsigned char *lut)
@@ -404,7 +419,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
     typedef typename AddrOf<W>::T T;
     constexpr int NR = FQ_SPAWN_NR;
     const int tid = threadIdx.x;
-    const SpawnOut<W> out(I, L, par, b);
+    const SpawnOut<W, EARLY> out(I, L, par, b);
     const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
     int top = 1;
     while (2 * top <= nS) top *= 2;
@@ -479,8 +494,14 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 pa0[r] = a0;
                 pa1[r] = a1;
                 kk[r] = k;
-                g[r] = out.group(dd);
-                rk[r] = out.rank(g[r]);
+                if (EARLY && fabs(v[r]) < I.theta) {
+                    const R4 rc = draw(I.seed, a0, a1, spawn_step, 4u + (k >> 28), k & 0x0fffffffu);
+                    v[r] = compress1(v[r], I.theta, rc.x);
+                }
+                if (!EARLY || v[r] != 0.0) {
+                    g[r] = out.group(dd);
+                    rk[r] = out.rank(g[r]);
+                }
             }
         }
         out.reserve();
@@ -504,7 +525,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
 // sums are compressed, the projected-energy terms of the bucket's reference
 // entries are accumulated, and the survivors are written to table[1-p]
 // together with the bucket's partial statistics.
-template <int W, int MODEL, int BS>
+template <int W, int MODEL, int BS, bool EARLY>
 __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 {
     typedef typename AddrOf<W>::T T;
@@ -600,7 +621,10 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     if (MODEL == 0) hii = narrow ? real_diag_runs<u32>(I.mc, (u32)t0[e]) : real_diag_runs(I.mc, a);
                     else hii = narrow ? mom_diag_modes<u32>(I.mc, (u32)t0[e]) : mom_diag_modes(I.mc, a);
                     const double g = 1.0 + I.dtau * (S - hii);
-                    lds_add<W>(L, I, t0[e], t1[e], tc[e] * g, b, nprobe);
+                    double w = tc[e] * g;
+                    if (EARLY && fabs(w) < I.theta)
+                        w = compress1(w, I.theta, draw(I.seed, t0[e], t1[e], (u32)(n + 1), 2u, 0u).x);
+                    if (w != 0.0) lds_add<W>(L, I, t0[e], t1[e], w, b, nprobe);
                 }
             }
         }
@@ -652,14 +676,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                         I.dmg_val[di] = w;
                     }
                 }
-                double aw = fabs(w);
-                if (aw >= I.theta) {
-                    cn = w;
-                } else if (aw > 0.0) {
-                    R4 r = draw(I.seed, a0, a1, (u32)(n + 1), 1u, 0u);
-                    double u = (double)r.x * 0x1p-32;
-                    if (u * I.theta < aw) cn = w < 0.0 ? -I.theta : I.theta;
-                }
+                cn = w;
+                if (!EARLY && w != 0.0 && fabs(w) < I.theta)
+                    cn = compress1(w, I.theta, draw(I.seed, a0, a1, (u32)(n + 1), 1u, 0u).x);
             }
             r0[k] = a0;
             r1[k] = a1;
@@ -764,7 +783,8 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 // |c| >= t_rel m, else ceil|c| picks); entries are ordered exact first by an
 // index permutation so that waves run one kind of unit; units of 4 attempts
 // are scanned and walked by spawn_units.
-template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *smem)
+template <int W, int MODEL, int BS, bool EARLY>
+__device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *smem)
 {
     typedef typename AddrOf<W>::T T;
     const int tid = threadIdx.x;
@@ -801,21 +821,18 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
     const int chunk = (nS + BS - 1) / BS;
     const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
     int n_ex = 0, bad = 0;
-    i64 nsp = 0;
     for (int i = i0; i < i1; i++) {
         const T a = AddrOf<W>::make(I.tab_a[par][0][tb + i], W == 2 ? I.tab_a[par][1][tb + i] : 0);
         u32 cnt;
         bool ex;
         spawn_info<W, MODEL>(I, a, I.tab_v[par][tb + i], cnt, ex, bad);
         info[2 * i] = cnt | (ex ? 0x80000000u : 0u);
-        nsp += cnt;
         n_ex += ex ? 1 : 0;
     }
     if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
     mark(5);
-    i64 tot_e, tot_sp;
+    i64 tot_e;
     i64 be = block_excl_scan<BS>(n_ex, L.misc, tot_e);
-    block_excl_scan<BS>(nsp, L.misc, tot_sp);
     i64 bs_ = (i64)i0 - be;  // stochastic entries before this thread's chunk
     for (int i = i0; i < i1; i++) {
         const u32 ce = info[2 * i];
@@ -824,12 +841,7 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
         info[2 * w + 1] = ce;
     }
     if (tid == 0) {
-        SpawnPart sp;
-        sp.exact = tot_e;
-        sp.inexact = nS - tot_e;
-        sp.spawns = tot_sp;
-        sp.pad = 0;
-        I.spart[spawn_step & 1][b] = sp;
+        L.misc[60] = 0;  // spawn records emitted by this bucket
         if (b == 0) ctrl->spawn_par = par;
     }
     __syncthreads();
@@ -848,9 +860,24 @@ template <int W, int MODEL, int BS> __device__ void spawn_bucket(const Inst &I, 
         if (tid == 0) set_error(ctrl, FQE_CAP_SLAB, b);
         return;
     }
+    // partial statistics: with late compression every attempt is a record;
+    // early compression counts the records that survive it
+    SpawnPart sp;
+    sp.exact = tot_e;
+    sp.inexact = nS - tot_e;
+    sp.spawns = atot;
+    sp.pad = 0;
+    if (!EARLY && tid == 0) I.spart[spawn_step & 1][b] = sp;
     __syncthreads();
     mark(6);
-    spawn_flat<W, MODEL, BS>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut);
+    spawn_flat<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut);
+    if (EARLY) {
+        __syncthreads();
+        if (tid == 0) {
+            sp.spawns = L.misc[60];
+            I.spart[spawn_step & 1][b] = sp;
+        }
+    }
     mark(7);
 }
 

@@ -29,7 +29,7 @@ def _flush(*a):
 
 def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2048, block=512,
              t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0,
-             spawn_block=None):
+             spawn_block=None, early=False):
     fq = _fq()
     spawn_block = block if spawn_block is None else spawn_block
     _flush(f"[one_step] model={model} M={M} N={N} W={W} n={n_entries} B={buckets} "
@@ -42,11 +42,12 @@ def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2
     assert np.array_equal(gaddr[:, 0], oaddr[:, 0])
     ref_o, ref_g = oaddr[0], gaddr[0]
     P = orc.params(model, M, N, t, u, dtau=dtau, target=1e4, theta=theta, t_rel=t_rel,
-                   seed=seed + 99)
+                   seed=seed + 99, early=early)
     o = orc.step(P, oaddr, vals, shift, step + 1, ref_o, 10.0, events=True, merged=True)
     cap_t = max(4096, 4 * len(occs))
     s = fq.Solver(model, M, N, t=t, u=u, dtau=dtau, target_walkers=1e4, threshold=theta,
-                  t_rel=t_rel, seed=seed + 99, addr_words=W, flags=3, table_capacity=cap_t,
+                  t_rel=t_rel, seed=seed + 99, addr_words=W,
+                  flags=3 | (fq.FLAG_EARLY_COMPRESSION if early else 0), table_capacity=cap_t,
                   spawn_capacity=max(8 * len(o["events"]), 65536), buckets=buckets,
                   lds_slots=slots, block=block, spawn_block=spawn_block)
     s.set_state(gaddr, vals, shift, step, ref=ref_g, yref=10.0)
@@ -148,11 +149,29 @@ def test_single_entry_state(orc):
     check_parity(*r)
 
 
-def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0):
+EARLY_CASES = [
+    # model, M, N, u, dtau, n, seed, W, buckets, slots, block, t_rel, theta
+    (0, 6, 6, 6.0, 1e-3, 200, 31, 1, 4, 1024, 256, 1.0, 1.0),
+    (1, 8, 8, 4.0, 1e-3, 1500, 32, 1, 8, 2048, 512, 1.0, 1.0),
+    (0, 20, 20, 6.0, 1e-3, 3000, 33, 2, 128, 2048, 1024, 1.0, 0.5),
+    (1, 10, 10, 4.0, 1e-3, 2500, 34, 1, 128, 2048, 1024, 0.0, 2.0),
+]
+
+
+@pytest.mark.parametrize("case", EARLY_CASES, ids=lambda c: f"early_m{c[0]}_M{c[1]}_W{c[7]}_B{c[8]}")
+def test_single_step_early_compression_bit_exact(orc, case):
+    model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel, theta = case
+    r = one_step(orc, model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel=t_rel, theta=theta,
+                 early=True, lo=0.01, hi=50.0)
+    check_parity(*r)
+
+
+def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0, early=False):
     fq = _fq()
     c = synthetic.CONFIGS["c1"]
     s = fq.Solver(c["model"], c["M"], c["N"], t=c["t"], u=c["u"], dtau=c["dtau"],
-                  target_walkers=c["target"], seed=c["seed"], addr_words=1, table_capacity=1024,
+                  target_walkers=c["target"], seed=c["seed"], addr_words=1,
+                  flags=fq.FLAG_EARLY_COMPRESSION if early else 0, table_capacity=1024,
                   spawn_capacity=8192, buckets=buckets, lds_slots=slots, block=block,
                   spawn_block=spawn_block)
     a = fq.start_address(c["model"], c["M"], c["N"])
@@ -162,14 +181,15 @@ def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0):
     return st
 
 
-def test_c1_trajectory_bit_exact_vs_oracle(orc):
+@pytest.mark.parametrize("early", [False, True], ids=["late", "early"])
+def test_c1_trajectory_bit_exact_vs_oracle(orc, early):
     """Config 1 end to end (1e4 steps): every statistics row of the GPU run
-    equals the oracle's bit for bit."""
-    _flush("[c1 trajectory] 10000 steps")
+    equals the oracle's bit for bit (late and early compression)."""
+    _flush(f"[c1 trajectory] 10000 steps, early={early}")
     c = synthetic.CONFIGS["c1"]
-    st = _c1_gpu(c["steps"])
+    st = _c1_gpu(c["steps"], early=early)
     P = orc.params(c["model"], c["M"], c["N"], c["t"], c["u"], dtau=c["dtau"], target=c["target"],
-                   seed=c["seed"])
+                   seed=c["seed"], early=early)
     a = orc.start_address(c["model"], c["M"], c["N"])
     ost, _, _ = orc.run(P, [a], [10.0], 0.0, 1, c["steps"], a, 10.0)
     for f in ost.dtype.names:
@@ -181,9 +201,10 @@ def test_c1_trajectory_bit_exact_vs_oracle(orc):
         assert len(bad) == 0, (f, bad[:5], g[bad[:5]], o[bad[:5]])
 
 
-def test_c1_energy_within_3_sigma_of_ed(orc):
+@pytest.mark.parametrize("early", [False, True], ids=["late", "early"])
+def test_c1_energy_within_3_sigma_of_ed(orc, early):
     from oracle import stats
-    st = _c1_gpu(10_000)
+    st = _c1_gpu(10_000, early=early)
     E0 = orc.eigs_sparse(orc.ham(0, 6, 6, 1.0, 6.0), 1)[0]
     se = stats.shift_estimator(st["shift"], skip=2000)
     pe = stats.projected_energy(st["hproj"], st["vproj"], skip=2000)
