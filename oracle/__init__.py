@@ -9,7 +9,9 @@ seeded input generators in ``synthetic``.
 Contents (paper sections in brackets):
 
 * Fock addresses, dimension and combinatorial ranking [Sec. 2, Sec. 6.1]
-* real- and momentum-space 1D Bose-Hubbard columns [Sec. 2, Sec. 6.2, 6.3]
+* real- and momentum-space 1D Bose-Hubbard columns [Sec. 2, Sec. 6.2, 6.3],
+  the periodic square lattice and Gutzwiller importance sampling [Sec. 3.3,
+  Sec. 7.2]
 * Philox4x32-10 counter-based draws (published definition, Salmon et al.)
 * one serial FCIQMC step and repeated steps [Sec. 3.1, 3.2, 7.1]
 * sparse-matrix and matrix-free Lanczos exact diagonalisation [Sec. 5]
@@ -31,11 +33,12 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 REAL1D = 0
 MOM1D = 1
+REAL2D = 2
 
 
 class Ham(C.Structure):
-    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("pad", C.c_int32),
-                ("t", C.c_double), ("u", C.c_double)]
+    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("lx", C.c_int32),
+                ("t", C.c_double), ("u", C.c_double), ("g", C.c_double)]
 
 
 class Params(C.Structure):
@@ -89,6 +92,8 @@ def lib():
         L.orc_fsum.argtypes = [f64p, C.c_int64]
         L.orc_column.restype = C.c_int
         L.orc_column.argtypes = [P(Ham), u64p, u64p, f64p, C.c_int, f64p]
+        L.orc_row.restype = C.c_int
+        L.orc_row.argtypes = [P(Ham), u64p, u64p, f64p, C.c_int]
         L.orc_shift_update.restype = C.c_double
         L.orc_shift_update.argtypes = [C.c_double] * 7
         L.orc_step.restype = C.c_int
@@ -214,8 +219,11 @@ def shift_update(S, N1, N0, Nt, zeta, xi, dtau):
 # Hamiltonians [Sec. 6.2]
 # --------------------------------------------------------------------------
 
-def ham(model, M, N, t=1.0, u=1.0):
-    return Ham(model, M, N, 0, float(t), float(u))
+def ham(model, M, N, t=1.0, u=1.0, lx=0, g=0.0):
+    """Hamiltonian: REAL1D ring of M sites, MOM1D with M modes, or REAL2D
+    periodic lx x (M / lx) lattice; g is the Gutzwiller importance-sampling
+    parameter of the real-space models [Sec. 3.3, Sec. 7.2]."""
+    return Ham(model, M, N, int(lx), float(t), float(u), float(g))
 
 
 def column(h, words, cap=1 << 16):
@@ -227,6 +235,18 @@ def column(h, words, cap=1 << 16):
     m = _check(lib().orc_column(C.byref(h), _p(a, C.c_uint64), _p(dest, C.c_uint64),
                                 _p(vals, C.c_double), cap, C.byref(diag)), "column")
     return diag.value, dest[:m].copy(), vals[:m].copy()
+
+
+def row(h, words, cap=1 << 16):
+    """(dests[m,2], values[m]): the row of `words` over its column's
+    destinations, H_{words,dest} (differs from the column only under
+    importance sampling)."""
+    a = np.asarray([int(words[0]), int(words[1])], np.uint64)
+    dest = np.zeros((cap, 2), np.uint64)
+    vals = np.zeros(cap, np.float64)
+    m = _check(lib().orc_row(C.byref(h), _p(a, C.c_uint64), _p(dest, C.c_uint64),
+                             _p(vals, C.c_double), cap), "row")
+    return dest[:m].copy(), vals[:m].copy()
 
 
 def sampled_pair(h, words, pi):
@@ -247,10 +267,10 @@ def validate(h):
 # --------------------------------------------------------------------------
 
 def params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target=1000.0, zeta=0.08, xi=None,
-           theta=1.0, t_rel=1.0, seed=0, early=False):
+           theta=1.0, t_rel=1.0, seed=0, early=False, lx=0, g=0.0):
     if xi is None:
         xi = zeta * zeta / 4.0
-    return Params(ham(model, M, N, t, u), dtau, target, zeta, xi, theta, t_rel, seed,
+    return Params(ham(model, M, N, t, u, lx, g), dtau, target, zeta, xi, theta, t_rel, seed,
                   1 if early else 0, 0)
 
 
@@ -404,8 +424,9 @@ def eigs_sparse(h, k=2):
 
 
 def start_address(model, M, N):
-    """Starting address: the uniform (near_uniform) state in real space; the
-    k = 0 condensate in momentum space (reading for the momentum model)."""
+    """Starting address: the uniform (near_uniform) state in real space (ring
+    or lattice, sites in index order); the k = 0 condensate in momentum space
+    (reading for the momentum model)."""
     if model == MOM1D:
         occ = [0] * M
         occ[0] = N

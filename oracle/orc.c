@@ -27,11 +27,13 @@
 #define ORC_ECAP -2
 #define ORC_ENOMEM -4
 
-enum { ORC_REAL1D = 0, ORC_MOM1D = 1 };
+enum { ORC_REAL1D = 0, ORC_MOM1D = 1, ORC_REAL2D = 2 };
 
 typedef struct {
-    int32_t model, M, N, pad;
+    int32_t model, M, N;
+    int32_t lx;      /* square lattice: sites per row (M = lx * ly); unused in 1D */
     double t, u;
+    double g;        /* Gutzwiller importance-sampling parameter (0: none) */
 } orc_ham;
 
 typedef struct {
@@ -300,23 +302,61 @@ static double real_diag(const orc_ham *H, const int32_t *occ)
     return (0.5 * H->u) * (double)s;
 }
 
-/* Real-space column.  Enumeration order (reading; the paper prints it only
- * for the uniform 12/12 state in Sec. 6.2): entry k < o moves one particle
- * from the k-th occupied site (ascending) to the next site on the ring,
- * entry k >= o moves one from the (k-o)-th occupied site to the previous
- * site.  Value -t sqrt(n_src (n_dst + 1)) with occupations before the hop.
- * For M = 2 both neighbours are the same site and appear twice. */
-static int real_column(const orc_ham *H, const int32_t *occ, orc_col *c)
+/* Neighbour of site s in direction dir on the periodic lattice.  Sites are
+ * numbered s = x + lx y (x fastest).  Directions (reading): 0 = +x, 1 = -x,
+ * 2 = +y, 3 = -y; the ring (1D, lx = M) has only the first two. */
+static int lattice_neighbour(const orc_ham *H, int s, int dir)
+{
+    int lx = H->model == ORC_REAL2D ? H->lx : H->M;
+    int ly = H->M / lx;
+    int x = s % lx, y = s / lx;
+    switch (dir) {
+    case 0: x = (x + 1) % lx; break;
+    case 1: x = (x - 1 + lx) % lx; break;
+    case 2: y = (y + 1) % ly; break;
+    default: y = (y - 1 + ly) % ly; break;
+    }
+    return x + lx * y;
+}
+
+/* Importance sampling with the Gutzwiller guiding function (Sec. 3.3, a
+ * similarity transformation by a diagonal matrix; Sec. 7.2 uses it).
+ * Reading: G = diag(exp(-g H_ii)) with H_ii the diagonal element (the
+ * interaction energy), H~ = G H G^-1, so H~_ij = H_ij exp(-g (H_ii - H_jj))
+ * for destination i and source j.  One boson hopping from a site holding n
+ * to one holding nd changes H_ii by u (nd - n + 1); the factor is
+ * exp(-(g u) k) with k = nd - n + 1 for the column (source -> destination)
+ * and k = -(nd - n + 1) for the row of the source. */
+static double gutzwiller_factor(const orc_ham *H, int k)
+{
+    if (H->g == 0.0) return 1.0;
+    return exp(-((H->g * H->u) * (double)k));
+}
+
+/* Real-space column on the ring (Eq. bose-hubbard-hamiltonian) or on the
+ * periodic square lattice.  Enumeration order (reading; the paper prints it
+ * only for the uniform 12/12 ring state in Sec. 6.2): entry k = dir o + i
+ * moves one particle from the i-th occupied site (ascending) to its
+ * neighbour in direction dir (o = occupied sites; on the ring k < o hops to
+ * the next site, k >= o to the previous one).  Value (-t sqrt(n_src (n_dst +
+ * 1))) times the Gutzwiller factor, occupations before the hop.  With
+ * row != 0 the values are those of the row of the source (the transposed
+ * similarity factor), used by the projected energy.  When two directions
+ * lead to the same site (a ring of 2 sites, a lattice 2 sites wide) the
+ * entry appears twice. */
+static int lattice_column(const orc_ham *H, const int32_t *occ, orc_col *c, int row)
 {
     int M = H->M;
+    int ndir = H->model == ORC_REAL2D ? 4 : 2;
     int list[ORC_MAXM], o = 0;
     for (int j = 0; j < M; j++) if (occ[j] > 0) list[o++] = j;
     int32_t tmp[ORC_MAXM];
-    for (int dir = 0; dir < 2; dir++) {
+    for (int dir = 0; dir < ndir; dir++) {
         for (int k = 0; k < o; k++) {
             int s = list[k];
-            int d = dir == 0 ? (s + 1) % M : (s - 1 + M) % M;
-            double h = (-H->t) * sqrt((double)(occ[s] * (occ[d] + 1)));
+            int d = lattice_neighbour(H, s, dir);
+            int kd = occ[d] - occ[s] + 1;
+            double h = ((-H->t) * sqrt((double)(occ[s] * (occ[d] + 1)))) * gutzwiller_factor(H, row ? -kd : kd);
             memcpy(tmp, occ, sizeof(int32_t) * (size_t)M);
             tmp[s] -= 1;
             tmp[d] += 1;
@@ -413,14 +453,24 @@ static double ham_diag(const orc_ham *H, const int32_t *occ)
 static int ham_column(const orc_ham *H, const int32_t *occ, orc_col *c)
 {
     memset(c, 0, sizeof *c);
-    return H->model == ORC_MOM1D ? mom_column(H, occ, c) : real_column(H, occ, c);
+    return H->model == ORC_MOM1D ? mom_column(H, occ, c) : lattice_column(H, occ, c, 0);
+}
+
+/* The off-diagonal entries of row `occ` (same destinations as its column;
+ * they differ only under importance sampling). */
+static int ham_row(const orc_ham *H, const int32_t *occ, orc_col *c)
+{
+    memset(c, 0, sizeof *c);
+    return H->model == ORC_MOM1D ? mom_column(H, occ, c) : lattice_column(H, occ, c, 1);
 }
 
 int orc_validate(const orc_ham *H)
 {
     if (H->M < 2 || H->M > ORC_MAXM || H->N < 1 || H->N + H->M - 1 > 127) return ORC_EINVAL;
-    if (H->model != ORC_REAL1D && H->model != ORC_MOM1D) return ORC_EINVAL;
-    if (H->model == ORC_MOM1D && H->M < 3) return ORC_EINVAL;
+    if (H->model != ORC_REAL1D && H->model != ORC_MOM1D && H->model != ORC_REAL2D) return ORC_EINVAL;
+    if (H->model == ORC_MOM1D && (H->M < 3 || H->g != 0.0)) return ORC_EINVAL;
+    if (H->model == ORC_REAL2D && (H->lx < 2 || H->M % H->lx != 0 || H->M / H->lx < 2)) return ORC_EINVAL;
+    if (!isfinite(H->g)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -435,6 +485,28 @@ int orc_column(const orc_ham *H, const uint64_t *a, uint64_t *dest, double *h, i
     *diag = ham_diag(H, occ);
     orc_col c;
     int rc = ham_column(H, occ, &c);
+    if (rc) { col_free(&c); return rc; }
+    int n = c.n;
+    if (n > cap) { col_free(&c); return ORC_ECAP; }
+    for (int k = 0; k < n; k++) {
+        dest[2 * k] = c.dest[k][0];
+        dest[2 * k + 1] = c.dest[k][1];
+        h[k] = c.h[k];
+    }
+    col_free(&c);
+    return n;
+}
+
+/* Exported row: the off-diagonal entries H_{a,dest} of the row of address a,
+ * with the destinations of its column in the same order (they differ from
+ * the column's values only under importance sampling). */
+int orc_row(const orc_ham *H, const uint64_t *a, uint64_t *dest, double *h, int cap)
+{
+    if (orc_validate(H)) return ORC_EINVAL;
+    int32_t occ[ORC_MAXM];
+    orc_decode(a, H->M, H->N, occ);
+    orc_col c;
+    int rc = ham_row(H, occ, &c);
     if (rc) { col_free(&c); return rc; }
     int n = c.n;
     if (n > cap) { col_free(&c); return ORC_ECAP; }
@@ -555,15 +627,16 @@ static double lookup(const uint64_t *addr, const double *val, int64_t n, const u
 
 /* Projected-energy numerator y H c and denominator y c for a reference
  * vector with a single nonzero entry y at address ref (Sec. 4.2).
- * hproj = sum over the column of ref (H symmetric) of y (H_k c_dest) plus
- * y (H_rr c_ref), summed exactly. */
+ * hproj = sum over the row of ref of y (H_rj c_j) plus y (H_rr c_ref),
+ * summed exactly.  The row has the destinations of the column of ref; its
+ * values equal the column's unless importance sampling makes H~ asymmetric. */
 static int proj_energy(const orc_params *P, const uint64_t *addr, const double *val, int64_t n,
                        const uint64_t *ref, double y, double *hproj, double *vproj)
 {
     int32_t occ[ORC_MAXM];
     orc_decode(ref, P->h.M, P->h.N, occ);
     orc_col c;
-    int rc = ham_column(&P->h, occ, &c);
+    int rc = ham_row(&P->h, occ, &c);
     if (rc) { col_free(&c); return rc; }
     double *terms = malloc(sizeof(double) * (size_t)(c.n + 1));
     if (!terms) { col_free(&c); return ORC_ENOMEM; }
