@@ -41,10 +41,17 @@ WORKLOADS = {
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
                table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=16384,
                lds_slots=2048, block=512, spawn_block=256, warmup=6000, steps=1000),
+    "c2d": dict(cfg="c2d", name="real2d_6x6_N36_u1_t0.1_g1_dtau1e-2_Nt1e7_W2",
+                table_capacity=30_000_000, spawn_capacity=60_000_000, buckets=16384,
+                lds_slots=2048, block=512, spawn_block=256, warmup=3000, steps=2000),
     "c1": dict(cfg="c1", name="real1d_M6_N6_u6_dtau1e-3_Nt1e3",
                table_capacity=1024, spawn_capacity=8192, buckets=0, lds_slots=0, block=0,
                spawn_block=0, warmup=0, steps=10_000),
 }
+
+
+MODEL_NAMES = {0: "real-space 1D Bose-Hubbard ring", 1: "momentum-space 1D Bose-Hubbard",
+               2: "real-space Bose-Hubbard on a periodic square lattice, Gutzwiller importance sampling"}
 
 
 def log(*a):
@@ -79,6 +86,7 @@ def measured_traffic(fq, kernel):
 def make_solver(fq, wl, cfg, **over):
     kw = dict(t=cfg["t"], u=cfg["u"], dtau=cfg["dtau"], target_walkers=cfg["target"],
               seed=cfg["seed"], addr_words=cfg["W"], threshold=cfg["theta"],
+              lx=cfg.get("lx", 0), g=cfg.get("g", 0.0),
               table_capacity=wl["table_capacity"], spawn_capacity=wl["spawn_capacity"],
               buckets=wl["buckets"], lds_slots=wl["lds_slots"], block=wl["block"],
               spawn_block=wl["spawn_block"])
@@ -94,7 +102,8 @@ def cpu_baseline(state, cfg, step_index, shift, budget_s=15.0):
     rng = np.random.default_rng(123)
     order = rng.permutation(n)
     P = oracle.params(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], dtau=cfg["dtau"],
-                      target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"])
+                      target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"],
+                      lx=cfg.get("lx", 0), g=cfg.get("g", 0.0))
     a2 = np.zeros((n, 2), np.uint64)
     a2[:, :addrs.shape[1]] = addrs
     ref = a2[int(np.argmax(np.abs(vals)))]
@@ -179,6 +188,48 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
                speedup_vs_plain=wall_p / wall_b, identical_to_plain=bool(same))
     log(f"[bench] batched {out['walker_steps_per_s']:.4g} walker-steps/s, plain "
         f"{out['plain_walker_steps_per_s']:.4g} ({out['speedup_vs_plain']:.2f}x), identical {same}")
+    return out
+
+
+PAPER_2D_STEPS_PER_S = 112.0  # Sec. 7.2: one CPU node, 32 threads, N_t = 1e7
+
+
+def bench_lattice(fq, torch, warmup=2000, steps=2000):
+    """The benchmark system of Sec. 7.2 (periodic 6 x 6 lattice, N = 36,
+    u = 1, t = 0.1, Gutzwiller importance sampling, N_t = 1e7): FCIQMC steps
+    per second at steady state, beside the paper's CPU figure (context: a
+    different machine; the paper times 5e4 steps after 2.5e4 equilibration
+    steps)."""
+    wl = WORKLOADS["c2d"]
+    cfg = synthetic.CONFIGS[wl["cfg"]]
+    s = make_solver(fq, wl, cfg)
+    a = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), cfg["W"])
+    s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup:
+        k = min(1000, warmup - done)
+        st = s.run(k)
+        done += k
+        log(f"[bench] lattice warmup {done}/{warmup}: norm {st['norm'][-1]:.4g} len {st['len'][-1]} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = s.run(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    s.close()
+    sps = steps / wall
+    out = dict(workload=wl["name"], model=MODEL_NAMES[cfg["model"]], warmup=warmup, steps=steps,
+               steps_per_s=sps, ms_per_step=wall / steps * 1e3,
+               walker_steps_per_s=float(st["norm"].sum()) / wall,
+               mean_len=float(st["len"].mean()), mean_spawns=float(st["spawns"].mean()),
+               shift_mean=float(st["shift"].mean()),
+               paper_context=dict(steps_per_s=PAPER_2D_STEPS_PER_S,
+                                  hardware="one CPU node, 32 threads, CPU model not stated"),
+               ratio_to_paper=sps / PAPER_2D_STEPS_PER_S)
+    log(f"[bench] lattice {sps:.1f} steps/s ({out['walker_steps_per_s']:.4g} walker-steps/s); "
+        f"paper {PAPER_2D_STEPS_PER_S:.0f} steps/s on 32 CPU threads")
     return out
 
 
@@ -340,6 +391,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the served measurement")
     ap.add_argument("--no-replicas", action="store_true", help="skip the replica-overlap measurement")
+    ap.add_argument("--no-lattice", action="store_true",
+                    help="skip the 6 x 6 lattice measurement (the paper's benchmark system)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-warmup", type=int, default=1500)
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -453,8 +506,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": wl["name"], "model": "momentum-space 1D Bose-Hubbard"
-                   if cfg["model"] == 1 else "real-space 1D Bose-Hubbard ring",
+        "config": {"workload": wl["name"], "model": MODEL_NAMES[cfg["model"]],
                    "M": cfg["M"], "N": cfg["N"], "u": cfg["u"], "dtau": cfg["dtau"],
                    "target_walkers": cfg["target"], "seed": cfg["seed"],
                    "addr_words": cfg["W"], "buckets": s.layout.buckets,
@@ -476,6 +528,9 @@ def main():
     s.close()
     del s
     torch.cuda.empty_cache()
+    if not args.no_lattice and args.workload == "c3":
+        out["lattice_2d"] = bench_lattice(fq, torch)
+        torch.cuda.empty_cache()
     if not args.no_replicas and args.workload == "c3":
         out["replicas"] = bench_replicas(fq, torch, wl, cfg, warmup=args.batch_warmup)
         torch.cuda.empty_cache()

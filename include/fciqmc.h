@@ -70,13 +70,29 @@ typedef enum {
     FQ_ENOTFOUND = -7   /* server: unknown request id                           */
 } fq_status;
 
-typedef enum { FQ_REAL1D = 0, FQ_MOM1D = 1 } fq_model;
+typedef enum { FQ_REAL1D = 0, FQ_MOM1D = 1, FQ_REAL2D = 2 } fq_model;
 
 /* Hamiltonian (Sec. 2 and Sec. 6.2): model, M modes, N bosons, hopping t,
- * on-site interaction u.  Momentum space requires M >= 3. */
+ * on-site interaction u.  Momentum space requires M >= 3.
+ *
+ * FQ_REAL2D is the Bose-Hubbard model on a periodic lx x (M / lx) square
+ * lattice (lx >= 2, M / lx >= 2; the workload of the benchmarks of Sec. 7.2),
+ * sites numbered x + lx y in address order.  Column entry k = dir o + i
+ * moves one boson from the i-th occupied site to its neighbour in direction
+ * dir = +x, -x, +y, -y (o = occupied sites; the ring has +x, -x), so a
+ * lattice 2 sites wide has each of those bonds twice.  lx is ignored by the
+ * other models.
+ *
+ * g: Gutzwiller importance sampling of the real-space models (Sec. 3.3, a
+ * similarity transformation by a diagonal matrix; Sec. 7.2): the sampled
+ * Hamiltonian is G H G^-1 with G = diag(exp(-g H_ii)), so a hop that moves a
+ * boson from a site holding n to one holding nd carries the factor
+ * exp(-(g u)(nd - n + 1)).  The walkers sample G c; the shift and the
+ * projected energy (with the row of G H G^-1) estimate the same energy.
+ * g = 0 is plain sampling; the momentum model requires g = 0. */
 typedef struct {
-    int32_t model, M, N, reserved;
-    double t, u;
+    int32_t model, M, N, lx;
+    double t, u, g;
 } fq_hamiltonian;
 
 /* Flags of fq_params.flags */
@@ -217,8 +233,9 @@ int fq_autotune(fq_handle *src, const fq_layout *candidates, int32_t n, int32_t 
  * Batch: n independent instances advanced together, one launch per kernel
  * per step for the whole batch (each workgroup finds its instance and bucket
  * from a map), with per-instance tables, shifts and statistics.  Instances
- * may differ in Hamiltonian (M, N, t, u), parameters and capacities; they
- * must share the model kind (real space, momentum space with M <= 16 or
+ * may differ in Hamiltonian (M, N, t, u, g), parameters and capacities;
+ * they must share the model kind (the ring without importance sampling; the
+ * square lattice or a ring with g != 0; momentum space with M <= 16 or
  * M <= 32), the compression style (FQ_FLAG_EARLY_COMPRESSION set or not),
  * addr_words, lds_slots, block and spawn_block.  Every instance
  * produces the same results as it would alone.
@@ -304,7 +321,7 @@ int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, do
  * requests of one server share the model, addr_words, lds_slots, block and
  * spawn_block of its configuration (momentum space: M <= 16) and use late
  * compression (a request with FQ_FLAG_EARLY_COMPRESSION is refused with
- * FQ_EINVAL).  Not thread safe.
+ * FQ_EINVAL); a ring server takes g = 0 only.  Not thread safe.
  * ------------------------------------------------------------------------ */
 typedef struct fq_server fq_server;
 typedef struct {

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfciqmc.so")
 
 REAL1D = 0
 MOM1D = 1
+REAL2D = 2
 
 FLAG_DUMP_SPAWNS = 1
 FLAG_DUMP_MERGED = 2
@@ -34,8 +35,8 @@ class FqError(RuntimeError):
 
 
 class Hamiltonian(C.Structure):
-    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("reserved", C.c_int32),
-                ("t", C.c_double), ("u", C.c_double)]
+    _fields_ = [("model", C.c_int32), ("M", C.c_int32), ("N", C.c_int32), ("lx", C.c_int32),
+                ("t", C.c_double), ("u", C.c_double), ("g", C.c_double)]
 
 
 class Params(C.Structure):
@@ -180,10 +181,10 @@ def _stream():
 
 
 def _ham_params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08, xi=None,
-                threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0):
+                threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0, lx=0, g=0.0):
     if xi is None:
         xi = zeta * zeta / 4.0
-    return (Hamiltonian(model, M, N, 0, float(t), float(u)),
+    return (Hamiltonian(model, M, N, int(lx), float(t), float(u), float(g)),
             Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words, flags))
 
 
@@ -198,12 +199,12 @@ class Solver:
     def __init__(self, model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08,
                  xi=None, threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0,
                  table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0,
-                 spawn_block=0):
+                 spawn_block=0, lx=0, g=0.0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the FCIQMC solver needs a GPU")
         self.ham, self.params = _ham_params(model, M, N, t, u, dtau, target_walkers, zeta, xi,
-                                            threshold, t_rel, seed, addr_words, flags)
+                                            threshold, t_rel, seed, addr_words, flags, lx, g)
         self.W = addr_words
         nbytes, lay = workspace_size(self.ham, self.params,
                                      _layout(table_capacity, spawn_capacity, buckets, lds_slots,
@@ -572,8 +573,8 @@ def source_digest():
 
 
 def start_address(model, M, N, W=1):
-    """Default starting address: the uniform state in real space, the k = 0
-    condensate in momentum space."""
+    """Default starting address: the uniform state in real space (ring or
+    lattice, sites in index order), the k = 0 condensate in momentum space."""
     if model == MOM1D:
         occ = [N] + [0] * (M - 1)
     else:

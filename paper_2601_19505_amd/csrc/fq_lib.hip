@@ -175,8 +175,10 @@ __global__ void k_take_norm(const Inst *Ip)
     c->acc_norm[0] = c->acc_norm[1] = 0;
 }
 
-// column of the reference address: entry 0 is the diagonal, then the
-// off-diagonal entries in column order; bucket of every destination
+// row of the reference address over its column's destinations: entry 0 is
+// the diagonal, then the off-diagonal entries in column order (equal to the
+// column's values unless importance sampling makes H asymmetric); bucket of
+// every destination
 template <int W, int MODEL>
 __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *ob, int *on, int cap)
 {
@@ -191,9 +193,9 @@ __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *
     const int o = popc(st);
     double hd;
     i64 m;
-    if (MODEL == 0) {
+    if (MODEL == 0 || MODEL == 3) {
         hd = real_diag_runs(I.mc, a);
-        m = 2 * o;
+        m = (MODEL == 0 ? 2 : I.mc.ndir) * o;
     } else {
         hd = mom_diag_modes(I.mc, a);
         m = mom_col_size(I.mc, a);
@@ -205,7 +207,17 @@ __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *
     ob[0] = (int)bucket_of(addr_hash(a), I.log2B);
     for (i64 e = 0; e < m; e++) {
         double h;
-        const T d = MODEL == 0 ? real_entry(I.mc, a, st, o, (int)e, h) : mom_column_entry(I.mc, a, (int)e, h, lut);
+        T d;
+        if (MODEL == 0) {
+            d = real_entry(I.mc, a, st, o, (int)e, h);
+        } else if (MODEL == 3) {
+            // the row of the reference: the inverse importance-sampling factor
+            int kd;
+            d = lat_entry(I.mc, a, st, o, (int)e, h, kd, lut);
+            h = h * I.mc.gz[I.mc.N - kd];
+        } else {
+            d = mom_column_entry(I.mc, a, (int)e, h, lut);
+        }
         oa[2 * (e + 1)] = word0(d);
         oa[2 * (e + 1) + 1] = word1(d);
         oh[e + 1] = h;
@@ -260,22 +272,30 @@ const void *pick_kernel(int bs, bool spawn, bool early)
     return early ? pick_bs<W, MODEL, true>(bs, spawn) : pick_bs<W, MODEL, false>(bs, spawn);
 }
 
-// kernel variant: 0 real space, 1 momentum space with M <= 16, 2 momentum
-// with M <= 32; plus 3 with early compression
-int variant(int model, int M, int flags)
+// kernel variant: 0 real-space ring, 1 momentum space with M <= 16, 2
+// momentum with M <= 32, 3 lattice (the square lattice, or the ring with
+// importance sampling); plus 4 with early compression
+int variant(int model, int M, double g, int flags)
 {
-    return (model == 0 ? 0 : (M <= 16 ? 1 : 2)) + ((flags & FQ_FLAG_EARLY_COMPRESSION) ? 3 : 0);
+    const int base = model == FQ_MOM1D ? (M <= 16 ? 1 : 2) : (model == FQ_REAL2D || g != 0.0) ? 3 : 0;
+    return base + ((flags & FQ_FLAG_EARLY_COMPRESSION) ? 4 : 0);
+}
+
+template <int W> const void *step_kernel_w(int m, int bs, bool spawn, bool e)
+{
+    switch (m) {
+    case 0: return pick_kernel<W, 0>(bs, spawn, e);
+    case 1: return pick_kernel<W, 1>(bs, spawn, e);
+    case 2: return pick_kernel<W, 2>(bs, spawn, e);
+    default: return pick_kernel<W, 3>(bs, spawn, e);
+    }
 }
 
 const void *step_kernel(int W, int var, int bs, bool spawn)
 {
-    const bool e = var >= 3;
-    const int m = var % 3;
-    if (W == 1)
-        return m == 0 ? pick_kernel<1, 0>(bs, spawn, e) : m == 1 ? pick_kernel<1, 1>(bs, spawn, e)
-                                                               : pick_kernel<1, 2>(bs, spawn, e);
-    return m == 0 ? pick_kernel<2, 0>(bs, spawn, e) : m == 1 ? pick_kernel<2, 1>(bs, spawn, e)
-                                                           : pick_kernel<2, 2>(bs, spawn, e);
+    const bool e = var >= 4;
+    const int m = var % 4;
+    return W == 1 ? step_kernel_w<1>(m, bs, spawn, e) : step_kernel_w<2>(m, bs, spawn, e);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -321,7 +341,7 @@ struct Resolved {
     int W, nb, B, log2B, slots, block, spawn_block, two_pass, log2G, log2SUB;
     i64 cap_t, cap_s, cap_c, dump_cap;
     size_t rec, slab_bytes;  // bytes per spawn record; bytes of one slab
-    size_t off_ctrl, off_inst, off_iptr, off_pmap, off_sq, off_eps, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
+    size_t off_ctrl, off_inst, off_iptr, off_pmap, off_sq, off_eps, off_nbr, off_gz, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
         off_tab_a[2][2], off_tab_v[2], off_tab_n[2], off_slab[2], off_slab_n[2], off_dsp_parent,
         off_dsp_attempt, off_dsp_dest, off_dsp_val, off_dmg_addr, off_dmg_val, off_part, off_spart[2], off_coarse,
         off_coarse_n, total;
@@ -331,9 +351,17 @@ struct Resolved {
 int validate(const fq_hamiltonian *h, const fq_params *p, std::string &err)
 {
     if (!h || !p) { err = "null argument"; return FQ_EINVAL; }
-    if (h->model != FQ_REAL1D && h->model != FQ_MOM1D) { err = "unknown model"; return FQ_EINVAL; }
+    if (h->model != FQ_REAL1D && h->model != FQ_MOM1D && h->model != FQ_REAL2D) { err = "unknown model"; return FQ_EINVAL; }
     if (h->M < 2 || h->N < 1) { err = "need M >= 2 and N >= 1"; return FQ_EINVAL; }
     if (h->model == FQ_MOM1D && (h->M < 3 || h->M > MOM_MAXM)) { err = "momentum model needs 3 <= M <= 32"; return FQ_EINVAL; }
+    if (h->model == FQ_REAL2D && (h->lx < 2 || h->M % h->lx != 0 || h->M / h->lx < 2)) {
+        err = "square lattice needs lx >= 2 and M / lx >= 2 rows of lx sites";
+        return FQ_EINVAL;
+    }
+    if (!std::isfinite(h->g) || (h->model == FQ_MOM1D && h->g != 0.0)) {
+        err = "g must be finite, and 0 for the momentum model";
+        return FQ_EINVAL;
+    }
     if (p->addr_words != 1 && p->addr_words != 2) { err = "addr_words must be 1 or 2"; return FQ_EINVAL; }
     int nb = h->N + h->M - 1;
     if (nb > (p->addr_words == 1 ? 62 : 126)) { err = "N+M-1 too large for addr_words"; return FQ_EINVAL; }
@@ -419,6 +447,8 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     R.off_pmap = take(sizeof(u32) << (R.log2G + R.log2SUB));
     R.off_sq = take(sizeof(double) * R.nsq);
     R.off_eps = take(sizeof(double) * MOM_MAXM);
+    R.off_nbr = take(4 * (size_t)h->M);
+    R.off_gz = take(sizeof(double) * (2 * (size_t)h->N + 1));
     R.off_ref_a = take(sizeof(u64) * 2 * REFCAP);
     R.off_ref_h = take(sizeof(double) * REFCAP);
     R.off_ref_b = take(sizeof(int) * REFCAP);
@@ -650,6 +680,9 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     I.mc.coef = h->u / (2.0 * (double)h->M);
     I.mc.sq = (const double *)(q->ws + R.off_sq);
     I.mc.eps = (const double *)(q->ws + R.off_eps);
+    I.mc.ndir = h->model == FQ_REAL2D ? 4 : 2;
+    I.mc.nbr = (const unsigned char *)(q->ws + R.off_nbr);
+    I.mc.gz = (const double *)(q->ws + R.off_gz);
     I.model = h->model;
     I.W = R.W;
     I.dtau = p->dtau;
@@ -704,10 +737,26 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
-    const void *km = step_kernel(R.W, variant(h->model, h->M, p->flags), R.block, false);
-    const void *ks = step_kernel(R.W, variant(h->model, h->M, p->flags), R.spawn_block, true);
+    const void *km = step_kernel(R.W, variant(h->model, h->M, h->g, p->flags), R.block, false);
+    const void *ks = step_kernel(R.W, variant(h->model, h->M, h->g, p->flags), R.spawn_block, true);
+    // lattice neighbours (sites x + lx y; +x, -x, +y, -y) and the
+    // importance-sampling factors gz[N + k] = exp(-(g u) k), k = -N .. N
+    const int lx = h->model == FQ_REAL2D ? h->lx : h->M, ly = h->M / lx;
+    std::vector<unsigned char> nbr(4 * (size_t)h->M, 0);
+    for (int site = 0; site < h->M; site++) {
+        const int x = site % lx, y = site / lx;
+        nbr[0 * h->M + site] = (unsigned char)((x + 1) % lx + lx * y);
+        nbr[1 * h->M + site] = (unsigned char)((x + lx - 1) % lx + lx * y);
+        nbr[2 * h->M + site] = (unsigned char)(x + lx * ((y + 1) % ly));
+        nbr[3 * h->M + site] = (unsigned char)(x + lx * ((y + ly - 1) % ly));
+    }
+    std::vector<double> gz(2 * (size_t)h->N + 1, 1.0);
+    if (h->g != 0.0)
+        for (int k = -h->N; k <= h->N; k++) gz[h->N + k] = std::exp(-((h->g * h->u) * (double)k));
     hipError_t e = hipMemcpy(q->ws + R.off_sq, sq.data(), sizeof(double) * R.nsq, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_eps, eps.data(), sizeof(double) * MOM_MAXM, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_nbr, nbr.data(), nbr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(q->ws + R.off_gz, gz.data(), sizeof(double) * gz.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(q->d_inst, &I, sizeof(Inst), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(q->ws + R.off_ctrl, 0, sizeof(Ctrl));
     const Inst *iptr = q->d_inst;
@@ -722,7 +771,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
     Exec &X = q->X;
     X.W = R.W;
-    X.var = variant(h->model, h->M, p->flags);
+    X.var = variant(h->model, h->M, h->g, p->flags);
     X.block = R.block;
     X.spawn_block = R.spawn_block;
     X.lds_m = lds_bytes(R.W, R.slots);
@@ -873,8 +922,9 @@ static int load_state(fq_handle *q, const u64 *sa, const double *sv, i64 n, doub
     int *rn = rb + REFCAP;
     u64 r0 = ref_addr[0], r1 = W == 2 ? ref_addr[1] : 0;
 #define REFK(W_, M_) hipLaunchKernelGGL((k_ref<W_, M_>), dim3(1), dim3(64), 0, s, (const Inst *)q->d_inst, r0, r1, ra, rh, rb, rn, REFCAP)
-    if (W == 1) { if (q->h.model == 0) REFK(1, 0); else REFK(1, 1); }
-    else { if (q->h.model == 0) REFK(2, 0); else REFK(2, 1); }
+    const int vm = variant(q->h.model, q->h.M, q->h.g, 0);
+    if (W == 1) { if (vm == 0) REFK(1, 0); else if (vm == 3) REFK(1, 3); else REFK(1, 1); }
+    else { if (vm == 0) REFK(2, 0); else if (vm == 3) REFK(2, 3); else REFK(2, 1); }
 #undef REFK
     HIPCHK(q, hipGetLastError());
     int m = 0;
@@ -1330,7 +1380,7 @@ int batch_plan(int n, const fq_hamiltonian *h, const fq_params *p, const fq_layo
         int rc = resolve(&h[i], &p[i], &lay[i], R, L, err);
         if (rc) { err = "batch instance " + std::to_string(i) + ": " + err; return rc; }
         if (i == 0) R0 = R;
-        if (R.W != R0.W || variant(h[i].model, h[i].M, p[i].flags) != variant(h[0].model, h[0].M, p[0].flags) ||
+        if (R.W != R0.W || variant(h[i].model, h[i].M, h[i].g, p[i].flags) != variant(h[0].model, h[0].M, h[0].g, p[0].flags) ||
             R.block != R0.block ||
             R.spawn_block != R0.spawn_block || R.slots != R0.slots) {
             err = "batch instance " + std::to_string(i) +
@@ -1444,7 +1494,9 @@ static int replica_check(fq_batch *b, std::string &err)
     for (int i = 1; i < n; i++) {
         const fq_handle *q = b->inst[i];
         if (q->h.model != q0->h.model || q->h.M != q0->h.M || q->h.N != q0->h.N ||
+            (q->h.model == FQ_REAL2D && q->h.lx != q0->h.lx) ||
             memcmp(&q->h.t, &q0->h.t, sizeof(double)) || memcmp(&q->h.u, &q0->h.u, sizeof(double)) ||
+            memcmp(&q->h.g, &q0->h.g, sizeof(double)) ||
             q->R.B != q0->R.B || q->R.W != q0->R.W || q->R.slots != q0->R.slots) {
             err = "replicas: instance " + std::to_string(i) +
                   " differs from instance 0 in its Hamiltonian, addr_words, buckets or lds_slots";
@@ -1676,6 +1728,10 @@ int fq_server_submit(fq_server *sv, const fq_hamiltonian *h, const fq_params *p,
     }
     if (p->flags & FQ_FLAG_EARLY_COMPRESSION) {
         sv->err = "submit: the server runs late compression only";
+        return FQ_EINVAL;
+    }
+    if (h->model == FQ_REAL1D && h->g != 0.0) {
+        sv->err = "submit: a ring server runs without importance sampling (g = 0)";
         return FQ_EINVAL;
     }
     Req r;

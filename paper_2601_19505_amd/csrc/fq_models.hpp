@@ -1,4 +1,4 @@
-// fq_models.hpp -- the two Bose-Hubbard Hamiltonians as device functions.
+// fq_models.hpp -- the Bose-Hubbard Hamiltonians as device functions.
 //
 // Column enumeration order, matrix elements and floating-point operation
 // order follow the conventions stated for the CPU reference so that spawn
@@ -36,6 +36,9 @@ struct ModelConst {
     double t, u, coef;          // coef = u / (2 M) (momentum)
     const double *sq;           // sq[k] = sqrt(k), correctly rounded, from the host
     const double *eps;          // eps[k] (momentum), from the host
+    int ndir;                   // lattice: hop directions (2 ring, 4 square lattice)
+    const unsigned char *nbr;   // lattice: nbr[dir M + site] = neighbouring site
+    const double *gz;           // lattice: gz[N + k] = exp(-(g u) k), from the host
 };
 
 // ---------------------------------------------------------------- real space
@@ -94,6 +97,46 @@ __device__ __forceinline__ T real_entry(const ModelConst &C, T a, T st, int o, i
     }
     h = (-C.t) * C.sq[n * (nd + 1)];
     return d;
+}
+
+// ---------------------------------------------------------------- lattice
+
+// remove bit x (higher bits move down) / insert a one at bit x (higher bits
+// move up)
+template <class T> __device__ __forceinline__ T del_bit(T a, int x)
+{
+    return (a & mask_below<T>(x)) | shl(shr(a, x + 1), x);
+}
+template <class T> __device__ __forceinline__ T ins_one(T a, int x)
+{
+    return (a & mask_below<T>(x)) | one_at<T>(x) | shl(shr(a, x), x + 1);
+}
+
+
+// Ring or periodic square lattice, with Gutzwiller importance sampling
+// (Sec. 3.3, Sec. 7.2).  Column entry k = dir o + i moves one boson from the
+// i-th occupied site to its neighbour in direction dir (+x, -x, +y, -y).
+// Returns the destination, h0 = (-t) sqrt(n_src (n_dst + 1)) and kd = n_dst
+// - n_src + 1; the matrix element is h0 gz[N + kd] in the column and
+// h0 gz[N - kd] in the row of the source.  The destination is the parent
+// with the first one of the source run removed and a one inserted at the
+// start of the destination run (whose start moves down by one when it lies
+// above the removed bit).
+template <class T>
+__device__ __forceinline__ T lat_entry(const ModelConst &C, T a, T st, int o, int k, double &h0, int &kd,
+                                       const unsigned char *lut)
+{
+    const int dir = (k >= o ? 1 : 0) + (k >= 2 * o ? 1 : 0) + (k >= 3 * o ? 1 : 0);
+    const int s = select_lut(st, k - dir * o, lut);
+    const int n = runlen(a, s);
+    const int j = s - popc(a & mask_below<T>(s));
+    const int dj = C.nbr[dir * C.M + j];
+    const T z = ~a & mask_below<T>(C.nb);
+    const int sd = dj == 0 ? 0 : select_lut(z, dj - 1, lut) + 1;
+    const int nd = runlen(a, sd);
+    kd = nd - n + 1;
+    h0 = (-C.t) * C.sq[n * (nd + 1)];
+    return ins_one(del_bit(a, s), sd > s ? sd - 1 : sd);
 }
 
 // ---------------------------------------------------------------- momentum
@@ -163,14 +206,6 @@ template <class T> __device__ __forceinline__ i64 mom_col_size(const ModelConst 
     return np * (M / 2) - (i64)o_odd * (o - o_odd);
 }
 
-template <class T> __device__ __forceinline__ T del_bit(T a, int x)
-{
-    return (a & mask_below<T>(x)) | shl(shr(a, x + 1), x);
-}
-template <class T> __device__ __forceinline__ T ins_one(T a, int x)
-{
-    return (a & mask_below<T>(x)) | one_at<T>(x) | shl(shr(a, x), x + 1);
-}
 
 // The move {p,q} -> {r,s} of a momentum-space parent a for the removal pair
 // starting at bits sp <= sq (modes p <= q, K = p + q mod M) and its di-th

@@ -315,6 +315,7 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
 {
     i64 m;
     if (MODEL == 0) m = 2 * popc(run_starts(a));
+    else if (MODEL == 3) m = I.mc.ndir * popc(run_starts(a));
     else if (W == 1 && I.mc.nb <= 32) m = mom_col_size<u32>(I.mc, (u32)word0(a));
     else m = mom_col_size(I.mc, a);
     double ac = fabs(c);
@@ -461,6 +462,11 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                     if (MODEL == 0) {
                         const T st = run_starts(a);
                         dd = real_entry(I.mc, a, st, popc(st), (int)k, h);
+                    } else if (MODEL == 3) {
+                        const T st = run_starts(a);
+                        int kd;
+                        dd = lat_entry(I.mc, a, st, popc(st), (int)k, h, kd, lut);
+                        h = h * I.mc.gz[I.mc.N + kd];
                     } else if (narrow) {
                         dd = AddrOf<W>::make((u64)mom_column_entry<u32>(I.mc, (u32)a0, (int)k, h, lut), 0);
                     } else {
@@ -477,6 +483,17 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                     const int o = popc(st);
                     dd = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)(2 * o)), h);
                     q = (double)(2 * o) / (double)cnt;
+                } else if (MODEL == 3) {
+                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
+                    const u32 k3 = k & 3;
+                    const u32 rw = k3 == 0 ? rr.x : k3 == 1 ? rr.y : k3 == 2 ? rr.z : rr.w;
+                    const T st = run_starts(a);
+                    const int o = popc(st);
+                    const int m = I.mc.ndir * o;
+                    int kd;
+                    dd = lat_entry(I.mc, a, st, o, (int)pick(rw, (u32)m), h, kd, lut);
+                    h = h * I.mc.gz[I.mc.N + kd];
+                    q = (double)m / (double)cnt;
                 } else {
                     const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
                     const bool odd = (k & 1) != 0;
@@ -618,7 +635,8 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                 if (i < nt) {
                     const T a = AddrOf<W>::make(t0[e], t1[e]);
                     double hii;
-                    if (MODEL == 0) hii = narrow ? real_diag_runs<u32>(I.mc, (u32)t0[e]) : real_diag_runs(I.mc, a);
+                    if (MODEL == 0 || MODEL == 3)
+                        hii = narrow ? real_diag_runs<u32>(I.mc, (u32)t0[e]) : real_diag_runs(I.mc, a);
                     else hii = narrow ? mom_diag_modes<u32>(I.mc, (u32)t0[e]) : mom_diag_modes(I.mc, a);
                     const double g = 1.0 + I.dtau * (S - hii);
                     double w = tc[e] * g;

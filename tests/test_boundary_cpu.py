@@ -46,8 +46,8 @@ def test_encode_rejects_overflow():
         fq.encode([40, 40], 1)
 
 
-def _ws(model=0, M=6, N=6, W=1, **kw):
-    h = fq.Hamiltonian(model, M, N, 0, 1.0, 6.0)
+def _ws(model=0, M=6, N=6, W=1, lx=0, g=0.0, **kw):
+    h = fq.Hamiltonian(model, M, N, lx, 1.0, 6.0, g)
     p = fq.Params(1e-3, 1e3, 0.08, 0.0016, 1.0, 1.0, 0, W, 0)
     lay = fq.Layout(kw.get("table", 1000), kw.get("spawn", 4000), kw.get("buckets", 0),
                     kw.get("slots", 0), kw.get("block", 0), kw.get("spawn_block", 0))
@@ -66,10 +66,21 @@ def test_workspace_size_and_defaults():
 
 @pytest.mark.parametrize("kw", [dict(M=1), dict(model=1, M=2, N=3), dict(M=40, N=30, W=1),
                                 dict(slots=3000), dict(block=128), dict(slots=8192, block=512),
-                                dict(buckets=3), dict(spawn_block=128), dict(spawn_block=2048)])
+                                dict(buckets=3), dict(spawn_block=128), dict(spawn_block=2048),
+                                dict(model=2, M=9, lx=1), dict(model=2, M=10, lx=3),
+                                dict(model=2, M=6, lx=6), dict(model=1, M=8, g=0.1),
+                                dict(g=float("nan")), dict(model=2, M=36, N=36, lx=6, W=1)])
 def test_workspace_size_rejects_invalid(kw):
     with pytest.raises(fq.FqError):
         _ws(**kw)
+
+
+def test_lattice_workspace_sizes():
+    """The 6 x 6 lattice with 36 bosons needs two address words (71 bits)."""
+    n, lay = _ws(model=2, M=36, N=36, lx=6, W=2, g=1.0, table=1000, spawn=4000)
+    assert n > 0
+    n1, _ = _ws(model=0, M=6, N=6, g=0.5)
+    assert n1 > 0
 
 
 def test_solver_fails_loudly_without_gpu():

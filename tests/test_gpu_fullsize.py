@@ -2,7 +2,8 @@
 times, on sampled outputs the oracle computes one by one.
 
 The vector is grown to its target (1e8 walkers for the momentum-space
-benchmark, 1e7 for the 20/20 real-space ring with two address words), then
+benchmark, 1e7 for the 20/20 real-space ring with two address words and for
+the 6 x 6 lattice of Sec. 7.2 with importance sampling), then
 two single steps run with sampled dumps (about 2^-k of all addresses).  For
 the sampled addresses the test checks, bit for bit:
 
@@ -64,7 +65,7 @@ def _pad2(a):
     return np.concatenate([a, np.zeros((len(a), 1), np.uint64)], 1)
 
 
-@pytest.mark.parametrize("name,k", [("c3", 12), ("c2", 10)])
+@pytest.mark.parametrize("name,k", [("c3", 12), ("c2", 10), ("c2d", 10)])
 def test_full_size_sampled_step(orc, name, k):
     import bench
     import paper_2601_19505_amd as fq
@@ -75,7 +76,7 @@ def test_full_size_sampled_step(orc, name, k):
     s = bench.make_solver(fq, wl, cfg, flags=flags)
     a0 = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), W)
     s.set_state([a0], [10.0], 0.0, 0, ref=a0, yref=10.0)
-    warm = 1500 if name == "c3" else 3000
+    warm = {"c3": 1500, "c2": 3000, "c2d": 2000}[name]
     _flush(f"[full size {name}] warmup {warm} steps, layout buckets={s.layout.buckets} "
            f"slots={s.layout.lds_slots} block={s.layout.block} spawn_block={s.layout.spawn_block}")
     done = 0
@@ -96,9 +97,10 @@ def test_full_size_sampled_step(orc, name, k):
            f"{len(mg[0])} sampled merged amplitudes")
     assert n2 == n1 + 1 and len(ev[0]) > 1000 and len(mg[0]) > 500
 
+    lx, g = cfg.get("lx", 0), cfg.get("g", 0.0)
     P = orc.params(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], dtau=cfg["dtau"],
-                   target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"])
-    h = orc.ham(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"])
+                   target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"], lx=lx, g=g)
+    h = orc.ham(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], lx=lx, g=g)
     par, att, dst, val = ev
     idx1 = _index(a1)
     # oracle events of the dumped parents
@@ -153,7 +155,8 @@ def test_full_size_sampled_step(orc, name, k):
     assert int(row["len"]) == len(v2)
     assert float(row["norm"]).hex() == float(orc.fsum(np.abs(v2))).hex()
     ref = _pad2(np.asarray([a0]))[0]
-    diag_r, dcol, hcol = orc.column(h, ref, cap=4096)
+    diag_r = orc.column(h, ref, cap=4096)[0]
+    dcol, hcol = orc.row(h, ref, cap=4096)  # y.Hc takes the row of the reference
     cref = _lookup(_index(a2), v2, np.asarray([a0]))[0]
     assert float(row["vproj"]).hex() == float(10.0 * cref).hex()
     ccol = _lookup(_index(a2), v2, dcol if W == 2 else dcol[:, :1])

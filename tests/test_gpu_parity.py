@@ -29,11 +29,11 @@ def _flush(*a):
 
 def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2048, block=512,
              t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0,
-             spawn_block=None, early=False):
+             spawn_block=None, early=False, lx=0, g=0.0):
     fq = _fq()
     spawn_block = block if spawn_block is None else spawn_block
-    _flush(f"[one_step] model={model} M={M} N={N} W={W} n={n_entries} B={buckets} "
-           f"slots={slots} block={block} spawn_block={spawn_block} t_rel={t_rel}")
+    _flush(f"[one_step] model={model} M={M} N={N} lx={lx} g={g} W={W} n={n_entries} B={buckets} "
+           f"slots={slots} block={block} spawn_block={spawn_block} t_rel={t_rel} early={early}")
     rng = np.random.default_rng(seed)
     occs = synthetic.random_occupations(rng, M, N, n_entries, momentum_sector=sector)
     vals = synthetic.random_amplitudes(rng, len(occs), lo=lo, hi=hi)
@@ -42,14 +42,14 @@ def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2
     assert np.array_equal(gaddr[:, 0], oaddr[:, 0])
     ref_o, ref_g = oaddr[0], gaddr[0]
     P = orc.params(model, M, N, t, u, dtau=dtau, target=1e4, theta=theta, t_rel=t_rel,
-                   seed=seed + 99, early=early)
+                   seed=seed + 99, early=early, lx=lx, g=g)
     o = orc.step(P, oaddr, vals, shift, step + 1, ref_o, 10.0, events=True, merged=True)
     cap_t = max(4096, 4 * len(occs))
     s = fq.Solver(model, M, N, t=t, u=u, dtau=dtau, target_walkers=1e4, threshold=theta,
                   t_rel=t_rel, seed=seed + 99, addr_words=W,
                   flags=3 | (fq.FLAG_EARLY_COMPRESSION if early else 0), table_capacity=cap_t,
                   spawn_capacity=max(8 * len(o["events"]), 65536), buckets=buckets,
-                  lds_slots=slots, block=block, spawn_block=spawn_block)
+                  lds_slots=slots, block=block, spawn_block=spawn_block, lx=lx, g=g)
     s.set_state(gaddr, vals, shift, step, ref=ref_g, yref=10.0)
     ev = s.spawn_dump()
     st = s.run(1)
@@ -164,6 +164,65 @@ def test_single_step_early_compression_bit_exact(orc, case):
     r = one_step(orc, model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel=t_rel, theta=theta,
                  early=True, lo=0.01, hi=50.0)
     check_parity(*r)
+
+
+LATTICE_CASES = [
+    # model, M, N, lx, g, t, u, dtau, n, seed, W, buckets, slots, block, t_rel, early
+    (2, 9, 9, 3, 0.0, 1.0, 2.0, 1e-3, 400, 41, 1, 4, 2048, 512, 1.0, False),
+    (2, 9, 9, 3, 0.5, 1.0, 2.0, 1e-3, 400, 42, 1, 4, 2048, 512, 1.0, False),
+    (2, 12, 10, 4, 0.3, 1.0, 1.0, 1e-3, 1500, 43, 2, 16, 2048, 1024, 0.5, False),
+    (2, 4, 5, 2, 0.2, 1.0, 2.0, 1e-2, 50, 46, 1, 1, 1024, 256, 1.0, False),
+    (2, 16, 12, 4, 0.5, 1.0, 1.0, 1e-3, 800, 47, 1, 32, 4096, 1024, 0.0, False),
+    (0, 8, 8, 0, 0.4, 1.0, 3.0, 1e-3, 600, 45, 1, 8, 2048, 512, 1.0, False),
+    (2, 9, 9, 3, 0.5, 1.0, 2.0, 1e-3, 400, 48, 1, 4, 2048, 512, 1.0, True),
+    # the benchmark system of Sec. 7.2 (6 x 6, N = 36, 71-bit addresses), two-pass partition
+    (2, 36, 36, 6, 1.0, 0.1, 1.0, 1e-2, 3000, 44, 2, 128, 4096, 1024, 1.0, False),
+]
+
+
+@pytest.mark.parametrize("case", LATTICE_CASES,
+                         ids=lambda c: f"lat_m{c[0]}_M{c[1]}_lx{c[3]}_g{c[4]}_W{c[10]}_B{c[11]}_e{int(c[15])}")
+def test_single_step_lattice_bit_exact(orc, case):
+    """Square lattice and Gutzwiller importance sampling (Sec. 3.3, Sec.
+    7.2): spawn events, merged sums, the compressed state and every
+    statistic (the projected energy through the row of the reference)
+    bit-identical to the oracle."""
+    model, M, N, lx, g, t, u, dtau, n, seed, W, B, slots, block, t_rel, early = case
+    r = one_step(orc, model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel=t_rel, t=t, lx=lx, g=g,
+                 early=early, lo=0.05 if not early else 0.01, hi=300.0 if not early else 50.0)
+    check_parity(*r)
+
+
+def test_small_lattice_trajectory_and_energies(orc):
+    """The 3 x 2 lattice with N = 6 at the couplings of the Sec. 7.2
+    benchmark (u = 1, t = 0.1, g = 1, dtau = 0.01, N_t = 1e3): all 1e4
+    statistics rows equal the oracle's bit for bit, and the shift and the
+    projected energy agree with exact diagonalisation within 3 sigma."""
+    from oracle import stats
+    fq = _fq()
+    c = synthetic.CONFIGS["c2d_small"]
+    _flush("[lattice trajectory] 3 x 2, N = 6, 10000 steps")
+    s = fq.Solver(c["model"], c["M"], c["N"], t=c["t"], u=c["u"], dtau=c["dtau"],
+                  target_walkers=c["target"], seed=c["seed"], addr_words=1, table_capacity=1024,
+                  spawn_capacity=8192, lx=c["lx"], g=c["g"])
+    a = fq.start_address(c["model"], c["M"], c["N"])
+    s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    st = s.run(c["steps"])
+    s.close()
+    P = orc.params(c["model"], c["M"], c["N"], c["t"], c["u"], dtau=c["dtau"], target=c["target"],
+                   seed=c["seed"], lx=c["lx"], g=c["g"])
+    oa = orc.start_address(c["model"], c["M"], c["N"])
+    ost, _, _ = orc.run(P, [oa], [10.0], 0.0, 1, c["steps"], oa, 10.0)
+    for f in ost.dtype.names:
+        assert st[f].tobytes() == ost[f].tobytes(), f
+    E0 = np.linalg.eigvalsh(orc.dense_matrix(orc.ham(c["model"], c["M"], c["N"], c["t"], c["u"],
+                                                     lx=c["lx"])))[0]
+    se = stats.shift_estimator(st["shift"], skip=2000)
+    pe = stats.projected_energy(st["hproj"], st["vproj"], skip=2000)
+    _flush(f"[lattice energies] shift {se.mean:.6f} +- {se.err:.6f}, projected {pe.ratio:.6f} +- "
+           f"{pe.err:.6f}, ED {E0:.8f}")
+    assert abs(se.mean - E0) < 3 * se.err
+    assert abs(pe.ratio - E0) < 3 * pe.err
 
 
 def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0, early=False):
