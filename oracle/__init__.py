@@ -15,7 +15,8 @@ Contents (paper sections in brackets):
 * Philox4x32-10 counter-based draws (published definition, Salmon et al.)
 * one serial FCIQMC step and repeated steps [Sec. 3.1, 3.2, 7.1]
 * sparse-matrix and matrix-free Lanczos exact diagonalisation [Sec. 5]
-* replica overlaps c_A . c_B [Sec. 4.3]
+* replica overlaps c_A . c_B [Sec. 4.3]; Gram-Schmidt orthogonalisation
+  of step-synchronised vectors for excited states [Sec. 2.2]
 * blocking analysis, shift estimator, ratio of means, variational energy
   [Sec. 4] (``stats``)
 
@@ -376,6 +377,67 @@ def overlap(addrs_a, vals_a, addrs_b, vals_b):
     va = np.asarray(vals_a, dtype=np.float64)[ia]
     vb = np.asarray(vals_b, dtype=np.float64)[ib]
     return math.fsum((va * vb).tolist())
+
+
+def orthogonalise(addrs_k, vals_k, addrs_j, vals_j):
+    """Gram-Schmidt projection c_k - (c_j . c_k / c_j . c_j) c_j [Sec. 2.2,
+    excited states by orthogonalising step-synchronised vectors].
+
+    c_j . c_k is the exactly rounded overlap and c_j . c_j the exactly
+    rounded sum of the rounded squares; their quotient alpha is one IEEE
+    division (0 when c_j is empty).  Each entry becomes v_k - (alpha v_j),
+    the product rounded first, with v_k = 0 where c_k has no entry; exact
+    zeros are dropped.  Returns (addrs, vals, alpha), c_k's entries first in
+    their order, then the new addresses in c_j's order.
+    """
+    import math
+    W = max(np.asarray(addrs_k).reshape(len(addrs_k), -1).shape[1] if len(addrs_k) else 1,
+            np.asarray(addrs_j).reshape(len(addrs_j), -1).shape[1] if len(addrs_j) else 1)
+    A = np.ascontiguousarray(np.asarray(addrs_k, dtype=np.uint64).reshape(len(addrs_k), W))
+    Bj = np.ascontiguousarray(np.asarray(addrs_j, dtype=np.uint64).reshape(len(addrs_j), W))
+    vk = np.asarray(vals_k, dtype=np.float64)
+    vj = np.asarray(vals_j, dtype=np.float64)
+    dot = overlap(A, vk, Bj, vj) if len(vk) and len(vj) else 0.0
+    nrm2 = math.fsum((vj * vj).tolist())
+    alpha = dot / nrm2 if nrm2 > 0.0 else 0.0
+    out = {}
+    order = []
+    for row, v in zip(A, vk):
+        key = row.tobytes()
+        out[key] = float(v)
+        order.append((key, row))
+    for row, v in zip(Bj, vj):
+        key = row.tobytes()
+        if key not in out:
+            out[key] = 0.0
+            order.append((key, row))
+        out[key] = out[key] - alpha * float(v)
+    keep = [(row, out[key]) for key, row in order if out[key] != 0.0]
+    addrs = np.array([r for r, _ in keep], dtype=np.uint64).reshape(len(keep), W)
+    vals = np.array([v for _, v in keep], dtype=np.float64)
+    return addrs, vals, alpha
+
+
+def spectral_run(Ps, starts, ref, nsteps, yref=10.0):
+    """R step-synchronised runs of one Hamiltonian (parameters Ps[r], 10
+    walkers on starts[r], shift 0, projected energy on ref): after every
+    step, vector k is orthogonalised against vectors 0 .. k-1 in turn [Sec.
+    2.2].  Returns the statistics rows (R, nsteps) of the steps (describing
+    the merged vectors before the orthogonalisation) and the final states."""
+    R = len(Ps)
+    st = [(_addr2([a]), np.array([10.0]), 0.0) for a in starts]
+    rows = [[] for _ in range(R)]
+    for n in range(nsteps):
+        for r in range(R):
+            addrs, vals, S = st[r]
+            o = step(Ps[r], addrs, vals, S, n + 1, ref, yref)
+            st[r] = (o["addr"], o["val"], o["stats"]["shift"])
+            rows[r].append(o["stats"])
+        for k in range(1, R):
+            for j in range(k):
+                a, v, _ = orthogonalise(st[k][0], st[k][1], st[j][0], st[j][1])
+                st[k] = (a, v, st[k][2])
+    return rows, st
 
 
 # --------------------------------------------------------------------------
