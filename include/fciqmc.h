@@ -301,6 +301,34 @@ int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, do
                           size_t scratch_bytes, int32_t *inexact, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Excited states (Sec. 2.2): a batch of R = 2 .. FQ_MAX_REPLICAS step-
+ * synchronised runs of one Hamiltonian (the same conditions as replicas),
+ * where after every merge run k is orthogonalised against runs 0 .. k-1 in
+ * turn (Gram-Schmidt): c_k <- c_k - alpha c_j with alpha = (c_j . c_k) /
+ * (c_j . c_j), both dot products summed exactly from rounded products (as
+ * the replica overlaps) and rounded once, alpha one IEEE division (0 for an
+ * empty c_j), each entry v_k - (alpha v_j) with the product rounded first
+ * over the union of the two supports, exact zeros dropped.  The projection
+ * happens before the spawn kernel reads the merged table, so every step
+ * starts from orthogonal vectors; the shift of run k then estimates the k-th
+ * energy level.  The statistics rows describe the merged vectors before the
+ * projection (as the shift update sees them); the next shift update starts
+ * from the exact 1-norm of the projected vector.
+ *
+ * fq_batch_spectral_scratch_size: bytes of device scratch (caller owned,
+ * 256-byte aligned).  FQ_EINVAL when the batch is not a valid set of runs
+ * or 2 * lds_slots does not fit the LDS of the projection.
+ * fq_batch_run_spectral: as fq_batch_run (stats may be NULL).  A bucket
+ * whose union does not fit the LDS hash or the table fails its run with
+ * FQ_ECAPACITY.  inexact (may be NULL) is set to 1 when a rounded product,
+ * square or projected value was not a multiple of 2^-96, so its exact sum
+ * was rounded first.
+ * ------------------------------------------------------------------------ */
+int fq_batch_spectral_scratch_size(fq_batch *b, size_t *bytes);
+int fq_batch_run_spectral(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *scratch, size_t scratch_bytes,
+                          int32_t *inexact, void *stream);
+
+/* ------------------------------------------------------------------------
  * Server: continuous batching of FCIQMC solves on one GPU.
  *
  * A request (Hamiltonian, parameters, capacities, start address with its

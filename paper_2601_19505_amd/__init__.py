@@ -128,6 +128,8 @@ def lib():
             "fq_batch_replica_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
             "fq_batch_run_replicas": (C.c_int, [vp, C.c_int64, vp, vp, vp, C.c_size_t,
                                                 C.POINTER(C.c_int32), vp]),
+            "fq_batch_spectral_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
+            "fq_batch_run_spectral": (C.c_int, [vp, C.c_int64, vp, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
             "fq_batch_destroy": (C.c_int, [vp]),
             "fq_server_create": (C.c_int, [P(ServerConfig), vp, C.c_size_t, P(vp)]),
             "fq_server_submit": (C.c_int, [vp, P(Hamiltonian), P(Params), P(Layout), u64p, C.c_double,
@@ -421,6 +423,7 @@ class Batch:
             raise FqError(rc, f"fq_batch_create: {lib().fq_last_error(None).decode()}")
         self.b = b
         self._ov = None
+        self._gs = None
         self._inst = []
         for i in range(n):
             h = C.c_void_p()
@@ -476,6 +479,32 @@ class Batch:
             err.stats, err.overlaps, err.instance = out, ovl, i
             raise err
         return out, ovl, bool(inexact.value)
+
+    def run_spectral(self, n_steps):
+        """Advance every instance as step-synchronised runs of one
+        Hamiltonian with run k orthogonalised against runs 0 .. k-1 after
+        every merge (excited states, Sec. 2.2).  Returns (stats of shape
+        (n, n_steps), inexact flag)."""
+        import torch
+        if self._gs is None:
+            nb = C.c_size_t(0)
+            rc = lib().fq_batch_spectral_scratch_size(self.b, C.byref(nb))
+            if rc:
+                raise FqError(rc, f"fq_batch_spectral_scratch_size: {lib().fq_batch_last_error(self.b).decode()}")
+            self._gs = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        out = np.zeros((self.n, n_steps), STATS_DTYPE)
+        inexact = C.c_int32(0)
+        rc = lib().fq_batch_run_spectral(self.b, n_steps, C.c_void_p(out.ctypes.data),
+                                         C.c_void_p(self._gs.data_ptr()), self._gs.numel(),
+                                         C.byref(inexact), _stream())
+        if rc:
+            i = lib().fq_batch_failed(self.b)
+            msg = (lib().fq_last_error(self._inst[i].h).decode() if i >= 0
+                   else lib().fq_batch_last_error(self.b).decode())
+            err = FqError(rc, f"fq_batch_run_spectral: {msg}")
+            err.stats, err.instance = out, i
+            raise err
+        return out, bool(inexact.value)
 
     def close(self):
         if getattr(self, "b", None):

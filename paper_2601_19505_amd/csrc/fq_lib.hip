@@ -130,6 +130,20 @@ template <int W> __global__ __launch_bounds__(OV_BS) void k_overlap(Overlap O)
     overlap_bucket<W, OV_BS>(O, (int)blockIdx.x / O.B, (int)blockIdx.x % O.B, smem);
 }
 __global__ __launch_bounds__(1024) void k_overlap_fin(Overlap O) { overlap_finalize<1024>(O); }
+// excited states: Gram-Schmidt projection of run k against run j, per bucket
+template <int W> __global__ __launch_bounds__(OV_BS) void k_gs_dot(Spectral S, int j, int k)
+{
+    extern __shared__ __align__(16) char smem[];
+    gs_dot<W, OV_BS>(S, j, k, (int)blockIdx.x, smem);
+}
+__global__ __launch_bounds__(1024) void k_gs_alpha(Spectral S, int j, int k) { gs_alpha<1024>(S, j, k); }
+template <int W> __global__ __launch_bounds__(OV_BS) void k_gs_update(Spectral S, int j, int k)
+{
+    extern __shared__ __align__(16) char smem[];
+    gs_update<W, OV_BS>(S, j, k, (int)blockIdx.x, smem);
+}
+// one workgroup per projected run k = 1 .. R-1
+__global__ __launch_bounds__(1024) void k_gs_norm(Spectral S) { gs_norm<1024>(S, (int)blockIdx.x + 1); }
 __global__ void k_fill_i32(int *p, int n, int v)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
@@ -525,10 +539,46 @@ hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s, hipEvent_t mid =
     return e;
 }
 
+// Excited-state runs: the Gram-Schmidt launches inside every step (all
+// instances of the group are the runs).
+struct GsRun {
+    Spectral S;
+    int W = 1;
+    size_t lds_dot = 0, lds_upd = 0;
+};
+
+size_t gs_dot_lds(int W, int slots) { return (size_t)(2 * slots) * (W == 2 ? 28 : 16) + sizeof(Fx3) * (OV_BS / 64); }
+size_t gs_upd_lds(int W, int slots)
+{
+    return (size_t)(2 * slots) * (W == 2 ? 28 : 16) + sizeof(Fx3) * (OV_BS / 64) + sizeof(i64) * (OV_BS / 64 + 1);
+}
+
+hipError_t launch_gs_projections(const GsRun &g, hipStream_t s)
+{
+    Spectral S = g.S;
+    const void *kd = g.W == 1 ? (const void *)k_gs_dot<1> : (const void *)k_gs_dot<2>;
+    const void *ku = g.W == 1 ? (const void *)k_gs_update<1> : (const void *)k_gs_update<2>;
+    hipError_t e = hipSuccess;
+    for (int k = 1; k < S.R && e == hipSuccess; k++) {
+        for (int j = 0; j < k && e == hipSuccess; j++) {
+            void *args[] = {(void *)&S, (void *)&j, (void *)&k};
+            e = hipLaunchKernel(kd, dim3(S.B), dim3(OV_BS), args, g.lds_dot, s);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_gs_alpha, dim3(1), dim3(1024), 0, s, S, j, k);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipLaunchKernel(ku, dim3(S.B), dim3(OV_BS), args, g.lds_upd, s);
+        }
+    }
+    return e;
+}
+
 // one step of every instance of X: merge, spawn, second partition pass,
 // finalize; with `ev`, NEV events: before the merge and after each of the
-// four kernels
-hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev)
+// four kernels.  With gs, the Gram-Schmidt projections run between the merge
+// and the spawn kernel, and the orthogonalised norms are set after the
+// finalize kernel.
+hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev, const GsRun *gs = nullptr)
 {
     hipError_t e = hipSuccess;
     if (ev) e = hipEventRecord(ev[0], s);
@@ -538,10 +588,15 @@ hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev)
         e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.block), args, X.lds_m, s);
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess && gs) e = launch_gs_projections(*gs, s);
     if (e == hipSuccess) e = launch_spawn(X, 0, s, ev ? ev[2] : nullptr);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_finalize, dim3(X.n), dim3(1024), 0, s, X.insts);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && gs) {
+        hipLaunchKernelGGL(k_gs_norm, dim3(gs->S.R - 1), dim3(1024), 0, s, gs->S);
         e = hipGetLastError();
     }
     if (ev && e == hipSuccess) e = hipEventRecord(ev[4], s);
@@ -1300,7 +1355,7 @@ hipError_t launch_overlap(const OvRun &ov, hipStream_t s)
 // rows appended at ov->out.  Returns the status of the first failing
 // instance (grid position in *failed) after the chunk in which it failed.
 int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStream_t s, int *failed, std::string &err,
-                OvRun *ov = nullptr)
+                OvRun *ov = nullptr, const GsRun *gs = nullptr)
 {
     const Exec &X = G.X;
     i64 launched = 0;
@@ -1310,7 +1365,7 @@ int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStre
         hipLaunchKernelGGL(k_begin_chunk, dim3(1), dim3(256), 0, s, X.insts, X.n);
         hipError_t e = hipGetLastError();
         for (i64 k = 0; k < chunk && e == hipSuccess; k++) {
-            e = exec_step(X, s, nullptr);
+            e = exec_step(X, s, nullptr, gs);
             if (e == hipSuccess && ov) e = launch_overlap(*ov, s);
         }
         if (e == hipSuccess) {
@@ -1591,6 +1646,109 @@ int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, do
     if (fl[0]) { b->err = "replicas: a table bucket does not fit the overlap hash (lds_slots)"; return FQ_ECAPACITY; }
     if (fl[2]) { b->err = "replicas: an amplitude product is out of the overlap range"; return FQ_EDIVERGED; }
     return FQ_OK;
+}
+
+struct GsScratch {
+    size_t rep, dots, norms, alpha, updated, flags, total;
+};
+
+static GsScratch gs_scratch(int R, int B)
+{
+    GsScratch o;
+    o.rep = 0;
+    o.dots = align256(sizeof(Inst *) * R);
+    o.norms = o.dots + align256(sizeof(Fx3) * 2 * (size_t)B);
+    o.alpha = o.norms + align256(sizeof(Fx3) * (size_t)R * B);
+    o.updated = o.alpha + 256;
+    o.flags = o.updated + align256(sizeof(int) * R);
+    o.total = o.flags + 256;
+    return o;
+}
+
+static int spectral_check(fq_batch *b, std::string &err)
+{
+    int rc = replica_check(b, err);
+    if (rc) return rc;
+    const fq_handle *q0 = b->inst[0];
+    if (gs_upd_lds(q0->R.W, q0->R.slots) > LDS_MAX) {
+        err = "excited states: lds_slots too large for the orthogonalisation hash (twice lds_slots)";
+        return FQ_EINVAL;
+    }
+    return FQ_OK;
+}
+
+int fq_batch_spectral_scratch_size(fq_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return FQ_EINVAL;
+    int rc = spectral_check(b, b->err);
+    if (rc) return rc;
+    *bytes = gs_scratch((int)b->inst.size(), b->inst[0]->R.B).total;
+    return FQ_OK;
+}
+
+int fq_batch_run_spectral(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *scratch, size_t scratch_bytes,
+                          int32_t *inexact, void *stream)
+{
+    if (!b || n_steps < 0) return FQ_EINVAL;
+    int rc = spectral_check(b, b->err);
+    if (rc) return rc;
+    const int R = (int)b->inst.size();
+    const fq_handle *q0 = b->inst[0];
+    const GsScratch lay = gs_scratch(R, q0->R.B);
+    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < lay.total) {
+        b->err = "excited states: scratch must be 256-byte aligned and at least fq_batch_spectral_scratch_size bytes";
+        return FQ_EINVAL;
+    }
+    for (int i = 0; i < R; i++) {
+        if (!b->inst[i]->have_state) { b->err = "excited states: run " + std::to_string(i) + " has no state"; return FQ_EINVAL; }
+        if (b->inst[i]->step != q0->step) { b->err = "excited states: runs are at different steps"; return FQ_EINVAL; }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *sc = (char *)scratch;
+    std::vector<const Inst *> rep(R);
+    for (int i = 0; i < R; i++) rep[i] = b->inst[i]->d_inst;
+    GsRun g;
+    g.W = q0->R.W;
+    g.lds_dot = gs_dot_lds(g.W, q0->R.slots);
+    g.lds_upd = gs_upd_lds(g.W, q0->R.slots);
+    g.S.rep = (const Inst *const *)(sc + lay.rep);
+    g.S.R = R;
+    g.S.B = q0->R.B;
+    g.S.dots = (Fx3 *)(sc + lay.dots);
+    g.S.norms = (Fx3 *)(sc + lay.norms);
+    g.S.alpha = (double *)(sc + lay.alpha);
+    g.S.updated = (int *)(sc + lay.updated);
+    g.S.flags = (int *)(sc + lay.flags);
+    hipError_t e = ensure_lds(g.W == 1 ? (const void *)k_gs_dot<1> : (const void *)k_gs_dot<2>, g.lds_dot);
+    if (e == hipSuccess)
+        e = ensure_lds(g.W == 1 ? (const void *)k_gs_update<1> : (const void *)k_gs_update<2>, g.lds_upd);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)g.S.rep, rep.data(), sizeof(Inst *) * R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, g.S.updated, R, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, g.S.flags, 4, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { b->err = std::string("excited states: ") + hipGetErrorString(e); return FQ_EHIP; }
+    hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(256), 0, s, b->G.X.insts, R, (i64)n_steps);
+    std::vector<fq_step_stats *> rows(R, nullptr);
+    if (stats)
+        for (int i = 0; i < R; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
+    int failed = -1;
+    b->failed = -1;
+    rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err, nullptr, &g);
+    if (failed >= 0)
+        for (int i = 0; i < R; i++)
+            if (b->pos[i] == failed) b->failed = i;
+    int fl[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(fl, g.S.flags, sizeof(fl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { b->err = std::string("excited states: ") + hipGetErrorString(e); return FQ_EHIP; }
+    if (inexact) *inexact = fl[0];
+    return rc;
 }
 
 const char *fq_batch_last_error(const fq_batch *b) { return b ? b->err.c_str() : g_err.c_str(); }

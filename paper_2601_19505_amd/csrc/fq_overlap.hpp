@@ -259,4 +259,225 @@ template <int BS> __device__ void overlap_finalize(const Overlap &O)
     }
 }
 
+// ------------------------------------------------ excited states
+//
+// Step-synchronised runs of one Hamiltonian, run k orthogonalised against
+// runs 0 .. k-1 in turn after every merge (Sec. 2.2, Gram-Schmidt): c_k <-
+// c_k - alpha c_j with alpha = (c_j . c_k) / (c_j . c_j).  The merged tables
+// (parity 1 - ctrl.parity while the step runs) are updated before the spawn
+// kernel reads them, so the next step starts from the orthogonal vector.
+// gs_dot: per bucket, c_j . c_k and c_j . c_j (products rounded, summed in
+// 192-bit fixed point); gs_alpha: one workgroup, the exactly rounded sums and
+// one division; gs_update: per bucket, the union of the two buckets in an
+// LDS hash of twice the merge's size, v_k - (alpha v_j) per address of c_j,
+// compaction of the non-zero values in slot order back into c_k's table and
+// the bucket's exact 1-norm; gs_norm (after the finalize kernel): that norm
+// becomes the norm the next shift update starts from.
+
+struct Spectral {
+    const Inst *const *rep;  // runs in caller order
+    int R, B;
+    Fx3 *dots;               // [B][2]: c_j . c_k, c_j . c_j of the pair being projected
+    Fx3 *norms;              // [R][B]: per-bucket 1-norm of c_k after its last projection
+    double *alpha;           // [1]
+    int *updated;            // [R]: run k was projected in the current step
+    int *flags;              // [0] inexact product or norm term
+};
+
+__device__ __forceinline__ bool gs_idle(const Spectral &S, int j, int k)
+{
+    return halted(S.rep[j]->ctrl) != 0 || halted(S.rep[k]->ctrl) != 0;
+}
+
+template <int W> __device__ __forceinline__ Lds gs_lds(char *smem, int slots)
+{
+    Lds L;
+    L.k0 = (u64 *)smem;
+    L.k1 = W == 2 ? (u64 *)(smem + 2 * sizeof(u64) * slots) : nullptr;
+    L.state = W == 2 ? (u32 *)(smem + 3 * sizeof(u64) * slots) : nullptr;
+    L.lo = L.hi = nullptr;
+    L.misc = nullptr;
+    L.mask = slots - 1;
+    return L;
+}
+// bytes of the hash in gs_lds layout: keys, values (after the keys), W = 2
+// second words and slot states
+template <int W> __device__ __forceinline__ size_t gs_lds_bytes(int slots)
+{
+    return (size_t)slots * (W == 2 ? 3 * sizeof(u64) + sizeof(u32) : 2 * sizeof(u64));
+}
+
+template <int W, int BS> __device__ void gs_dot(const Spectral &S, const int j, const int k, const int b, char *smem)
+{
+    if (gs_idle(S, j, k)) return;
+    const Inst &IJ = *S.rep[j], &IK = *S.rep[k];
+    const int slots = 2 * IJ.slots;  // a projected run may hold the union of two buckets
+    Lds L = gs_lds<W>(smem, slots);
+    double *val = (double *)(smem + sizeof(u64) * slots);
+    Fx3 *tmp = (Fx3 *)(smem + gs_lds_bytes<W>(slots));
+    __shared__ int s_full;
+    const int tid = threadIdx.x;
+    for (int s = tid; s < slots; s += BS) {
+        L.k0[s] = EMPTY;
+        if (W == 2) { L.k1[s] = EMPTY; L.state[s] = 0u; }
+    }
+    if (tid == 0) s_full = 0;
+    __syncthreads();
+    const int pj = 1 - IJ.ctrl->parity, pk = 1 - IK.ctrl->parity;
+    const i64 nJ = min((i64)IJ.tab_n[pj][b], IJ.cap_t), nK = min((i64)IK.tab_n[pk][b], IK.cap_t);
+    const i64 bj = (i64)b * IJ.cap_t, bk = (i64)b * IK.cap_t;
+    int inexact = 0, ovf = 0, np = 0;
+    Fx3 sq = fx3_zero();
+    for (i64 i = tid; i < nJ; i += BS) {
+        u64 a0, a1;
+        double v;
+        tab_entry<W>(IJ, pj, bj + i, a0, a1, v);
+        const int s = lds_slot<W>(L, a0, a1, addr_hash(AddrOf<W>::make(a0, a1)), np);
+        if (s < 0) s_full = 1;
+        else val[s] = v;
+        fx3_add(sq, to_fx3(v * v, inexact, ovf));
+    }
+    __syncthreads();
+    if (s_full && tid == 0) set_error(IK.ctrl, FQE_CAP_LDS, b);
+    Fx3 dot = fx3_zero();
+    for (i64 i = tid; i < nK; i += BS) {
+        u64 a0, a1;
+        double v;
+        tab_entry<W>(IK, pk, bk + i, a0, a1, v);
+        const int s = lds_find<W>(L, a0, a1, addr_hash(AddrOf<W>::make(a0, a1)));
+        if (s >= 0) fx3_add(dot, to_fx3(val[s] * v, inexact, ovf));
+    }
+    const Fx3 d = block_sum_fx3<BS>(dot, tmp);
+    const Fx3 q = block_sum_fx3<BS>(sq, tmp);
+    if (tid == 0) {
+        S.dots[2 * (i64)b] = d;
+        S.dots[2 * (i64)b + 1] = q;
+    }
+    if (inexact) atomicOr(&S.flags[0], 1);
+    if (ovf) set_error(IK.ctrl, FQE_DIVERGED, b);
+}
+
+template <int BS> __device__ void gs_alpha(const Spectral &S, const int j, const int k)
+{
+    __shared__ Fx3 tmp[BS / 64];
+    if (gs_idle(S, j, k)) return;
+    const int tid = threadIdx.x;
+    Fx3 d = fx3_zero(), q = fx3_zero();
+    for (int b = tid; b < S.B; b += BS) {
+        fx3_add(d, S.dots[2 * (i64)b]);
+        fx3_add(q, S.dots[2 * (i64)b + 1]);
+    }
+    const Fx3 ds = block_sum_fx3<BS>(d, tmp);
+    const Fx3 qs = block_sum_fx3<BS>(q, tmp);
+    if (tid == 0) {
+        const double nq = from_fx3(qs);
+        *S.alpha = nq > 0.0 ? from_fx3(ds) / nq : 0.0;
+    }
+}
+
+template <int W, int BS> __device__ void gs_update(const Spectral &S, const int j, const int k, const int b, char *smem)
+{
+    if (gs_idle(S, j, k)) return;
+    const Inst &IJ = *S.rep[j], &IK = *S.rep[k];
+    const int slots = 2 * IK.slots;  // the union of two buckets
+    Lds L = gs_lds<W>(smem, slots);
+    double *val = (double *)(smem + sizeof(u64) * slots);
+    char *rest = smem + gs_lds_bytes<W>(slots);
+    Fx3 *tmp = (Fx3 *)rest;
+    i64 *scan = (i64 *)(rest + sizeof(Fx3) * (BS / 64));
+    __shared__ int s_full;
+    const int tid = threadIdx.x;
+    for (int s = tid; s < slots; s += BS) {
+        L.k0[s] = EMPTY;
+        if (W == 2) { L.k1[s] = EMPTY; L.state[s] = 0u; }
+        val[s] = 0.0;
+    }
+    if (tid == 0) s_full = 0;
+    __syncthreads();
+    const int pj = 1 - IJ.ctrl->parity, pk = 1 - IK.ctrl->parity;
+    const i64 nJ = min((i64)IJ.tab_n[pj][b], IJ.cap_t), nK = min((i64)IK.tab_n[pk][b], IK.cap_t);
+    const i64 bj = (i64)b * IJ.cap_t, bk = (i64)b * IK.cap_t;
+    int np = 0;
+    for (i64 i = tid; i < nK; i += BS) {
+        u64 a0, a1;
+        double v;
+        tab_entry<W>(IK, pk, bk + i, a0, a1, v);
+        const int s = lds_slot<W>(L, a0, a1, addr_hash(AddrOf<W>::make(a0, a1)), np);
+        if (s < 0) s_full = 1;
+        else val[s] = v;
+    }
+    __syncthreads();
+    const double alpha = *S.alpha;
+    for (i64 i = tid; i < nJ; i += BS) {
+        u64 a0, a1;
+        double v;
+        tab_entry<W>(IJ, pj, bj + i, a0, a1, v);
+        const int s = lds_slot<W>(L, a0, a1, addr_hash(AddrOf<W>::make(a0, a1)), np);
+        if (s < 0) {
+            s_full = 1;
+        } else {
+            const double p = alpha * v;
+            val[s] = val[s] - p;
+        }
+    }
+    __syncthreads();
+    if (s_full) {
+        if (tid == 0) set_error(IK.ctrl, FQE_CAP_LDS, b);
+        return;
+    }
+    // compaction in slot order: thread t owns slots [t c, (t + 1) c)
+    const int per = slots / BS;
+    const int s0 = tid * per;
+    i64 mine = 0;
+    for (int s = s0; s < s0 + per; s++) {
+        const bool occ = W == 1 ? L.k0[s] != EMPTY : L.state[s] == 2u;
+        mine += (occ && val[s] != 0.0) ? 1 : 0;
+    }
+    i64 total;
+    i64 o = block_excl_scan<BS>(mine, scan, total);
+    int inexact = 0, ovf = 0;
+    Fx3 nrm = fx3_zero();
+    if (total > IK.cap_t) {
+        if (tid == 0) set_error(IK.ctrl, FQE_CAP_TABLE, b);
+        return;
+    }
+    for (int s = s0; s < s0 + per; s++) {
+        const bool occ = W == 1 ? L.k0[s] != EMPTY : L.state[s] == 2u;
+        if (occ && val[s] != 0.0) {
+            IK.tab_a[pk][0][bk + o] = L.k0[s];
+            if (W == 2) IK.tab_a[pk][1][bk + o] = L.k1[s];
+            IK.tab_v[pk][bk + o] = val[s];
+            fx3_add(nrm, to_fx3(fabs(val[s]), inexact, ovf));
+            o++;
+        }
+    }
+    const Fx3 ns = block_sum_fx3<BS>(nrm, tmp);
+    if (tid == 0) {
+        IK.tab_n[pk][b] = (int)total;
+        S.norms[(i64)k * S.B + b] = ns;
+        if (b == 0) S.updated[k] = 1;
+    }
+    if (inexact) atomicOr(&S.flags[0], 1);
+    if (ovf) set_error(IK.ctrl, FQE_DIVERGED, b);
+}
+
+// after the finalize kernel: the orthogonalised norm of every projected run
+template <int BS> __device__ void gs_norm(const Spectral &S, const int k)
+{
+    __shared__ Fx3 tmp[BS / 64];
+    __shared__ int s_go;
+    const int tid = threadIdx.x;
+    Ctrl *c = S.rep[k]->ctrl;
+    if (tid == 0) s_go = S.updated[k] && __hip_atomic_load(&c->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    __syncthreads();
+    if (!s_go) return;
+    Fx3 a = fx3_zero();
+    for (int b = tid; b < S.B; b += BS) fx3_add(a, S.norms[(i64)k * S.B + b]);
+    const Fx3 t = block_sum_fx3<BS>(a, tmp);
+    if (tid == 0) {
+        c->norm = from_fx3(t);
+        S.updated[k] = 0;
+    }
+}
+
 }  // namespace fq
