@@ -441,13 +441,15 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
             pa0[r] = pa1[r] = 0;
             kk[r] = 0;
             if (kf < A) {
+                // A < 2^32 (checked by the caller): 32-bit offsets suffice
+                const u32 k32 = (u32)kf;
                 int lo = 0;
                 for (int stp = top; stp > 0; stp >>= 1) {
                     const int nx = lo + stp;
-                    if (nx < nS && (i64)info[2 * (w0_ + nx)] <= kf) lo = nx;
+                    if (nx < nS && info[2 * (w0_ + nx)] <= k32) lo = nx;
                 }
                 const int w = w0_ + lo;
-                const u32 k = (u32)(kf - (i64)info[2 * w]);
+                const u32 k = k32 - info[2 * w];
                 const u32 cw = info[2 * w + 1];
                 const u32 cnt = cw & 0x7fffffffu;
                 const i64 e = (i64)b * I.cap_t + perm[w];
