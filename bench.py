@@ -83,6 +83,32 @@ def measured_traffic(fq, kernel):
     return total if seen == {"FETCH_SIZE", "WRITE_SIZE"} else None
 
 
+VALU_PROFILE = os.path.join(ROOT, "profiles", "step_kernels_mom1d_M16N16_1e8_valu_instructions.txt")
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs x
+# 2.4 GHz, one instruction per SIMD every 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def measured_valu(fq, kernel):
+    """VALU instructions per launch of `kernel` from the committed
+    SQ_INSTS_VALU summary, or None when absent or taken with other kernel
+    sources."""
+    try:
+        with open(VALU_PROFILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = [ln.split(":", 1)[1].strip() for ln in lines if ln.startswith("# kernel source sha256:")]
+    if not digest or digest[0] != fq.source_digest():
+        return None
+    for i, ln in enumerate(lines):
+        if ln.startswith("void " + kernel + "<") and i + 1 < len(lines):
+            nxt = lines[i + 1].split()
+            if nxt and nxt[0] == "SQ_INSTS_VALU":
+                return float(nxt[1])
+    return None
+
+
 def make_solver(fq, wl, cfg, **over):
     kw = dict(t=cfg["t"], u=cfg["u"], dtau=cfg["dtau"], target_walkers=cfg["target"],
               seed=cfg["seed"], addr_words=cfg["W"], threshold=cfg["theta"],
@@ -491,6 +517,12 @@ def main():
     kern["partition"]["achieved_GBs"] = (kern["partition"]["algorithmic_bytes"] /
                                          max(kern["partition"]["mean_ms"], 1e-9) / 1e6)
     kern["finalize"] = {"mean_ms": kms["finalize"] / max(nl, 1)}
+    if args.workload == "c3":
+        for k in ("merge", "spawn"):
+            vi = measured_valu(fq, "k_" + k)
+            if vi is not None:
+                kern[k]["valu_insts_per_launch"] = vi
+                kern[k]["valu_issue_frac"] = vi / (kern[k]["mean_ms"] * 1e-3) / VALU_ISSUE_PEAK
     dom = max(per_kernel, key=lambda k: kern[k]["mean_ms"])
     achieved = kern[dom]["achieved_GBs"]
     out = {
