@@ -67,9 +67,10 @@ __global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u3
 }
 
 // one workgroup per instance
-__global__ __launch_bounds__(1024) void k_finalize(const Inst *const *insts)
+constexpr int FIN_BS = 256;  // threads of the finalize workgroup
+__global__ __launch_bounds__(FIN_BS) void k_finalize(const Inst *const *insts)
 {
-    finalize_instance<1024>(*insts[blockIdx.x]);
+    finalize_instance<FIN_BS>(*insts[blockIdx.x]);
 }
 
 // Second partition pass; map entry = instance << 14 | coarse sub-slab.  The
@@ -592,7 +593,7 @@ hipError_t exec_step(const Exec &X, hipStream_t s, hipEvent_t *ev, const GsRun *
     if (e == hipSuccess) e = launch_spawn(X, 0, s, ev ? ev[2] : nullptr);
     if (ev && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_finalize, dim3(X.n), dim3(1024), 0, s, X.insts);
+        hipLaunchKernelGGL(k_finalize, dim3(X.n), dim3(FIN_BS), 0, s, X.insts);
         e = hipGetLastError();
     }
     if (e == hipSuccess && gs) {
