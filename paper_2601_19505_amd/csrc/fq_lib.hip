@@ -334,8 +334,9 @@ size_t lds_bytes(int W, int slots)
 }
 
 // spawn kernel: three 32-bit words per table entry (unit offset, count word,
-// permutation), the scratch words and the 2048-byte select table
-size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048; }
+// permutation), the scratch words, the 2048-byte select table and the coarse
+// parent index
+size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048 + sizeof(int) * SPAWN_COARSE; }
 
 constexpr size_t LDS_MAX = 160 * 1024;
 static_assert(sizeof(Ctrl) % 4 == 0, "Ctrl is copied in 32-bit words");

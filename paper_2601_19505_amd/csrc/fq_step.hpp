@@ -405,25 +405,44 @@ template <int W, bool COUNT> struct SpawnOut {
 // first, attempt offsets in info[2 w], count word with the exact flag in
 // info[2 w + 1]) are enumerated flat: in each round thread t takes attempts
 // base + r BS + t (r < NR), finds each attempt's parent by a binary search
-// with a fixed number of steps and generates the record with branch-free
+// over the short range a coarse index of the bucket leaves and generates the record with branch-free
 // code, so all lanes of a wave do the same work (only the one round that
 // holds the boundary mixes the two kinds).  NR records per thread and round
 // make the runs appended to each destination group longer.
 #ifndef FQ_SPAWN_NR
 #define FQ_SPAWN_NR 4
 #endif
+constexpr int SPAWN_COARSE = 512;  // entries of the coarse parent index of a bucket
+
 template <int W, int MODEL, int BS, bool EARLY>
 __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const int b, const int par,
                                            const u32 spawn_step, const int w0_, const int nS, const u32 *info,
-                                           const u32 *perm, const i64 A, const unsigned char *lut)
+                                           const u32 *perm, const i64 A, const unsigned char *lut, int *coarse)
 {
     typedef typename AddrOf<W>::T T;
     constexpr int NR = FQ_SPAWN_NR;
     const int tid = threadIdx.x;
     const SpawnOut<W, EARLY> out(I, L, par, b);
     const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
+    // Coarse index: coarse[j] is the parent of attempt j 2^cs (the last entry
+    // whose first attempt is at or before it), for j < nc.  The parent of
+    // attempt k then lies between coarse[k >> cs] and the next coarse entry,
+    // a short range searched per attempt.
     int top = 1;
     while (2 * top <= nS) top *= 2;
+    int cs = 5;
+    while ((A >> cs) >= SPAWN_COARSE) cs++;
+    const int nc = (int)(A >> cs) + 1;
+    for (int j = tid; j < nc; j += BS) {
+        const u32 kj = (u32)((i64)j << cs);  // A < 2^32 (checked by the caller)
+        int lo = 0;
+        for (int stp = top; stp > 0; stp >>= 1) {
+            const int nx = lo + stp;
+            if (nx < nS && info[2 * (w0_ + nx)] <= kj) lo = nx;
+        }
+        coarse[j] = lo;
+    }
+    __syncthreads();
     for (i64 base = 0; base < A; base += (i64)NR * BS) {
         out.begin();
         T d[NR];
@@ -443,10 +462,12 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
             if (kf < A) {
                 // A < 2^32 (checked by the caller): 32-bit offsets suffice
                 const u32 k32 = (u32)kf;
-                int lo = 0;
-                for (int stp = top; stp > 0; stp >>= 1) {
-                    const int nx = lo + stp;
-                    if (nx < nS && info[2 * (w0_ + nx)] <= k32) lo = nx;
+                const int j = (int)(kf >> cs);
+                int lo = coarse[j], hi = j + 1 < nc ? coarse[j + 1] : nS - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (info[2 * (w0_ + mid)] <= k32) lo = mid;
+                    else hi = mid - 1;
                 }
                 const int w = w0_ + lo;
                 const u32 k = k32 - info[2 * w];
@@ -890,7 +911,8 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     if (!EARLY && tid == 0) I.spart[spawn_step & 1][b] = sp;
     __syncthreads();
     mark(6);
-    spawn_flat<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut);
+    spawn_flat<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut,
+                                    (int *)(lut + 2048));
     if (EARLY) {
         __syncthreads();
         if (tid == 0) {
