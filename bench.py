@@ -429,8 +429,8 @@ def main():
                          "that many bytes): the reference kernel for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md but not implemented",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; sharding over several "
+                                   "GPUs is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -20,9 +20,8 @@ Contents (paper sections in brackets):
 * blocking analysis, shift estimator, ratio of means, variational energy
   [Sec. 4] (``stats``)
 
-Parity status of every function is listed in the design doc; every function here
-is pinned by a ``-m "not gpu"`` test against the paper's printed values,
-closed forms or independent library routines.
+Every function here is pinned by a ``-m "not gpu"`` test against the
+paper's printed values, closed forms or independent library routines.
 """
 import ctypes as C
 import os

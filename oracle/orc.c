@@ -8,8 +8,7 @@
  *
  * Everything is fp64, compiled without floating-point contraction and without
  * fast-math.  Each function cites the passage of the paper it follows.  Where
- * the paper is silent the reading taken is stated in the comment (and listed
- * in the design doc of the repository).
+ * the paper is silent the reading taken is stated in the comment.
  *
  * Address convention (Sec. 6.1, bitstring representation of BoseFS): a Fock
  * state |n_1 ... n_M> is a string of N+M-1 bits; mode 1 occupies the lowest

@@ -5,15 +5,15 @@ oracle and the GPU library) encodes and processes them with its own code.
 
 Workloads (all t = 1, threshold 1, 1D periodic Bose-Hubbard):
 
-* C1 real space M = N = 6, u = 6, dtau = 1e-3, N_t = 1e3, 1e4 steps, seed 0,
+* `c1`: real space M = N = 6, u = 6, dtau = 1e-3, N_t = 1e3, 1e4 steps, seed 0,
   uniform start with 10 walkers;
-* C2 real space M = N = 20, u = 6, dtau = 1e-3, N_t = 1e7, 2e4 steps, seed 1,
+* `c2`: real space M = N = 20, u = 6, dtau = 1e-3, N_t = 1e7, 2e4 steps, seed 1,
   128-bit (W = 2) addresses;
-* C3 momentum space M = N = 16, u = 4, dtau = 5e-4, N_t = 1e8, 5e3 steps,
+* `c3`: momentum space M = N = 16, u = 4, dtau = 5e-4, N_t = 1e8, 5e3 steps,
   seed 2, start from the k = 0 condensate with 10 walkers;
-* C4 64 real-space instances, M = N uniform in 8..24, u log-uniform in
+* the batch: 64 real-space instances, M = N uniform in 8..24, u log-uniform in
   [1, 10], N_t log-linear in log D mapped into [1e4, 1e7], seeds 1000 + i;
-* C5 a Poisson stream (rate 50/s) of real-space solves, M = N in 6..20,
+* the stream: a Poisson stream (rate 50/s) of real-space solves, M = N in 6..20,
   u uniform in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7];
 * the benchmark system of Sec. 7.2: the periodic 6 x 6 square lattice with
   N = 36, u = 1, t = 0.1, Gutzwiller importance sampling (g = 1, reading),

@@ -242,8 +242,9 @@ def _c1_gpu(steps, buckets=0, slots=0, block=0, spawn_block=0, early=False):
 
 @pytest.mark.parametrize("early", [False, True], ids=["late", "early"])
 def test_c1_trajectory_bit_exact_vs_oracle(orc, early):
-    """Config 1 end to end (1e4 steps): every statistics row of the GPU run
-    equals the oracle's bit for bit (late and early compression)."""
+    """The 6/6 ring at u = 6 (N_t = 1e3) end to end (1e4 steps): every
+    statistics row of the GPU run equals the oracle's bit for bit (late and
+    early compression)."""
     _flush(f"[c1 trajectory] 10000 steps, early={early}")
     c = synthetic.CONFIGS["c1"]
     st = _c1_gpu(c["steps"], early=early)

@@ -60,9 +60,9 @@ def test_replica_overlaps_bit_exact(orc, R, W, buckets, M, u, target, steps):
 
 
 def test_replicas_c1_variational_energy_within_3_sigma_of_ed(orc):
-    """Two replicas of config 1 for 1e4 steps: the overlap series equals the
-    oracle's bit for bit and the variational energy agrees with exact
-    diagonalisation within three standard errors."""
+    """Two replicas of the 6/6 ring at u = 6 (N_t = 1e3) for 1e4 steps: the
+    overlap series equals the oracle's bit for bit and the variational
+    energy agrees with exact diagonalisation within three standard errors."""
     import paper_2601_19505_amd as fq
     b = _replicas(fq, 2, [0, 1])
     st, ov, _ = b.run_replicas(10000)

@@ -186,7 +186,7 @@ def test_ratio_of_means_linear_propagation():
 
 
 def test_c1_oracle_energies_within_3_sigma_of_ed(orc):
-    """Config 1: 6/6, u = 6, dtau 1e-3, target 1e3, 1e4 steps, seed 0."""
+    """The 6/6 ring: u = 6, dtau 1e-3, target 1e3, 1e4 steps, seed 0."""
     P = orc.params(orc.REAL1D, 6, 6, 1.0, 6.0, dtau=1e-3, target=1e3, seed=0)
     a = orc.start_address(orc.REAL1D, 6, 6)
     st, _, _ = orc.run(P, [a], [10.0], 0.0, 1, 10000, a, 10.0)
