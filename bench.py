@@ -354,9 +354,14 @@ def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
                         "[1e3, 1e7]), continuous batching",
                requests=n_req, pool_bytes=pool, steps_per_tick=tick, ticks=ticks,
                p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
-               walker_steps_per_s=ws / makespan, makespan_s=makespan, all_done=bool(ok))
+               walker_steps_per_s=ws / makespan, makespan_s=makespan, all_done=bool(ok),
+               mean_walker_steps_per_request=ws / n_req,
+               # largest arrival rate whose work the GPU keeps up with (beyond
+               # it the queue, and the p99 latency, grow without bound)
+               capacity_requests_per_s=(ws / makespan) / (ws / n_req))
     log(f"[bench] served p50 {out['p50_latency_s']:.2f} s p99 {out['p99_latency_s']:.2f} s, "
-        f"{out['walker_steps_per_s']:.4g} walker-steps/s")
+        f"{out['walker_steps_per_s']:.4g} walker-steps/s, capacity {out['capacity_requests_per_s']:.2f} "
+        f"requests/s")
     return out
 
 
