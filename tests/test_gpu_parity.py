@@ -175,6 +175,8 @@ LATTICE_CASES = [
     (2, 16, 12, 4, 0.5, 1.0, 1.0, 1e-3, 800, 47, 1, 32, 4096, 1024, 0.0, False),
     (0, 8, 8, 0, 0.4, 1.0, 3.0, 1e-3, 600, 45, 1, 8, 2048, 512, 1.0, False),
     (2, 9, 9, 3, 0.5, 1.0, 2.0, 1e-3, 400, 48, 1, 4, 2048, 512, 1.0, True),
+    # the largest two-word address: a 9 x 7 lattice with N = 64 (126 bits)
+    (2, 63, 64, 9, 0.3, 1.0, 1.0, 1e-3, 500, 49, 2, 8, 2048, 512, 1.0, False),
     # the benchmark system of Sec. 7.2 (6 x 6, N = 36, 71-bit addresses), two-pass partition
     (2, 36, 36, 6, 1.0, 0.1, 1.0, 1e-2, 3000, 44, 2, 128, 4096, 1024, 1.0, False),
 ]

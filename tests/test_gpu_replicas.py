@@ -40,10 +40,11 @@ def _replicas(fq, R, seeds, M=6, N=6, u=6.0, dtau=1e-3, target=1e3, W=1, table=1
     (2, 1, 0, 6, 6.0, 1e3, 1000),
     (3, 2, 4, 6, 6.0, 1e3, 400),
     (2, 1, 64, 8, 3.0, 5e3, 400),
+    (8, 1, 2, 5, 4.0, 3e2, 200),  # the largest replica set, 28 pairs
 ])
 def test_replica_overlaps_bit_exact(orc, R, W, buckets, M, u, target, steps):
     import paper_2601_19505_amd as fq
-    seeds = [0, 1, 5]
+    seeds = [0, 1, 5, 6, 7, 8, 9, 10]
     _flush(f"[replicas] R={R} W={W} buckets={buckets} M=N={M} u={u} steps={steps}")
     b = _replicas(fq, R, seeds, M=M, N=M, u=u, target=target, W=W, buckets=buckets,
                   table=16384, spawn=131072)

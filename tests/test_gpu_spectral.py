@@ -50,10 +50,11 @@ def _state_map(addrs, vals):
     (2, 1, 0, 0, 6, 6, 6.0, 0, 0.0, 2000),
     (3, 2, 4, 0, 6, 6, 6.0, 0, 0.0, 500),
     (2, 1, 8, 2, 6, 6, 1.0, 3, 1.0, 500),
+    (4, 1, 2, 0, 5, 5, 3.0, 0, 0.0, 300),
 ])
 def test_spectral_runs_bit_exact(orc, R, W, buckets, model, M, N, u, lx, g, steps):
     import paper_2601_19505_amd as fq
-    seeds = [0, 1, 2]
+    seeds = [0, 1, 2, 3]
     h = orc.ham(model, M, N, 1.0, u, lx=lx, g=g)
     a = orc.start_address(model, M, N)
     col = orc.column(h, a)[1]
