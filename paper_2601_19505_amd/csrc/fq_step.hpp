@@ -249,27 +249,25 @@ template <int W> __device__ __forceinline__ int lds_slot(const Lds &L, u64 a0, u
     for (int probe = 0; probe <= L.mask; probe++) {
         np++;
         if (W == 1) {
-            u64 k = __hip_atomic_load(&L.k0[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (k == a0) return s;
-            if (k == EMPTY) {
-                u64 old = atomicCAS((unsigned long long *)&L.k0[s], EMPTY, a0);
-                if (old == EMPTY || old == a0) return s;
-            }
+            // one compare-and-swap per probe: it claims an empty slot, and
+            // returns the key already there otherwise
+            const u64 old = atomicCAS((unsigned long long *)&L.k0[s], EMPTY, a0);
+            if (old == EMPTY || old == a0) return s;
         } else {
             for (;;) {
-                u32 st = __hip_atomic_load(&L.state[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                // claim an empty slot (0 -> 1), or learn its state: 2 full,
+                // 1 busy while another lane writes the key
+                u32 st = 0u;
+                if (__hip_atomic_compare_exchange_strong(&L.state[s], &st, 1u, __ATOMIC_ACQUIRE, __ATOMIC_ACQUIRE,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                    L.k0[s] = a0;
+                    L.k1[s] = a1;
+                    __hip_atomic_store(&L.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    return s;
+                }
                 if (st == 2u) {
                     if (L.k0[s] == a0 && L.k1[s] == a1) return s;
                     break;
-                }
-                if (st == 0u) {
-                    u32 old = atomicCAS(&L.state[s], 0u, 1u);
-                    if (old == 0u) {
-                        L.k0[s] = a0;
-                        L.k1[s] = a1;
-                        __hip_atomic_store(&L.state[s], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        return s;
-                    }
                 }
                 // busy: another lane is writing the key; look again
             }
@@ -292,11 +290,26 @@ template <int W> __device__ __forceinline__ int lds_find(const Lds &L, u64 a0, u
     return -1;
 }
 
+// Slot of an address in the merge's LDS hash: a 32-bit finalizer (two
+// multiplies) of the address words folded to 32 bits.  The bucket is chosen
+// by the top bits of the 64-bit address hash; inside a bucket any well-mixed
+// function serves, and this one costs a third of the instructions.
+__device__ __forceinline__ u64 slot_hash(u64 a0, u64 a1)
+{
+    u32 x = (u32)a0 ^ ((u32)(a0 >> 32) * 0x85EBCA6Bu) ^ ((u32)a1 * 0xC2B2AE35u) ^ ((u32)(a1 >> 32) * 0x27D4EB2Fu);
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return (u64)x;
+}
+
 template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Inst &I, u64 a0, u64 a1,
                                                         double v, int b, int &np)
 {
     typedef typename AddrOf<W>::T T;
-    u64 h = addr_hash(AddrOf<W>::make(a0, a1));
+    u64 h = slot_hash(a0, W == 2 ? a1 : 0ull);
     int s = lds_slot<W>(L, a0, a1, h, np);
     if (s < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); return; }
     u64 lo, hi;
@@ -740,8 +753,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             for (int e = r_beg + tid; e < r_end; e += BS) {
                 u64 a0 = I.ref_a[0][e];
                 u64 a1 = W == 2 ? I.ref_a[1][e] : 0;
-                u64 h = addr_hash(AddrOf<W>::make(a0, a1));
-                int s = lds_find<W>(L, a0, a1, h);
+                int s = lds_find<W>(L, a0, a1, slot_hash(a0, W == 2 ? a1 : 0ull));
                 double cv = s >= 0 ? bitsd(L.lo[s]) : 0.0;
                 double term = I.yref * (I.ref_h[e] * cv);
                 u64 lo, hi;
