@@ -22,6 +22,25 @@ typedef unsigned long long u64;
 typedef long long i64;
 typedef uint32_t u32;
 
+// ---------------------------------------------------------------- global memory
+
+// The descriptors hold generic pointers.  Hot accesses of device memory go
+// through these views, so that they compile to global (not flat) memory
+// instructions: flat loads also count against the LDS wait counter, so every
+// wait for an LDS result would drain the HBM loads in flight as well.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FQ_GAS __attribute__((address_space(1)))
+#else
+#define FQ_GAS  // the host pass only parses device functions
+#endif
+template <class T> __device__ __forceinline__ const FQ_GAS T *gmem(const T *p) { return (const FQ_GAS T *)p; }
+template <class T> __device__ __forceinline__ FQ_GAS T *gmem(T *p) { return (FQ_GAS T *)p; }
+// device-scope relaxed add (the ordering of atomicAdd) on device memory
+__device__ __forceinline__ int gatomic_add(int *p, int v)
+{
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------- bits
 
 __device__ __forceinline__ u64 dbits(double d) { return (u64)__double_as_longlong(d); }

@@ -35,15 +35,26 @@ using namespace fq;
 // its instance and bucket through `map` (entry = instance << 14 | bucket);
 // without a map there is one instance and workgroup b takes bucket b.
 
+// Kernels never write a descriptor, so a workgroup reads its descriptor in
+// the constant address space: scalar loads, loaded once rather than again
+// after every store the kernel makes, and the pointers it holds are known to
+// address device memory (global, not flat, loads and stores).  The integer
+// round trip keeps the compiler from folding the cast away.
+typedef const __attribute__((address_space(4))) Inst ConstInst;
+__device__ __forceinline__ const Inst &const_inst(const Inst *p)
+{
+    return *(const Inst *)(ConstInst *)(uintptr_t)p;
+}
+
 __device__ __forceinline__ const Inst &locate(const Inst *const *insts, const u32 *map, int &b)
 {
     if (map) {
         const u32 m = map[blockIdx.x];
         b = (int)(m & 0x3fffu);
-        return *insts[m >> 14];
+        return const_inst(insts[m >> 14]);
     }
     b = (int)blockIdx.x;
-    return *insts[0];
+    return const_inst(insts[0]);
 }
 
 // EARLY: early compression (separate kernels, so the late-compression
@@ -70,7 +81,7 @@ __global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u3
 constexpr int FIN_BS = 256;  // threads of the finalize workgroup
 __global__ __launch_bounds__(FIN_BS) void k_finalize(const Inst *const *insts)
 {
-    finalize_instance<FIN_BS>(*insts[blockIdx.x]);
+    finalize_instance<FIN_BS>(const_inst(insts[blockIdx.x]));
 }
 
 // Second partition pass; map entry = instance << 14 | coarse sub-slab.  The
@@ -91,7 +102,7 @@ constexpr int PART_RPT = FQ_PART_RPT;  // records per thread and round
 template <int W> __global__ __launch_bounds__(PART_BS) void k_part(const Inst *const *insts, const u32 *map)
 {
     const u32 m = map[blockIdx.x];
-    partition_coarse<W, PART_BS, PART_RPT>(*insts[m >> 14], (int)(m & 0x3fffu));
+    partition_coarse<W, PART_BS, PART_RPT>(const_inst(insts[m >> 14]), (int)(m & 0x3fffu));
 }
 
 // start of a chunk of steps: statistics rows are stored from row 0

@@ -95,7 +95,7 @@ __device__ __forceinline__ T real_entry(const ModelConst &C, T a, T st, int o, i
             d = shr(a, 1) | one_at<T>(nb - 1);
         }
     }
-    h = (-C.t) * C.sq[n * (nd + 1)];
+    h = (-C.t) * gmem(C.sq)[n * (nd + 1)];
     return d;
 }
 
@@ -130,12 +130,12 @@ __device__ __forceinline__ T lat_entry(const ModelConst &C, T a, T st, int o, in
     const int s = select_lut(st, k - dir * o, lut);
     const int n = runlen(a, s);
     const int j = s - popc(a & mask_below<T>(s));
-    const int dj = C.nbr[dir * C.M + j];
+    const int dj = gmem(C.nbr)[dir * C.M + j];
     const T z = ~a & mask_below<T>(C.nb);
     const int sd = dj == 0 ? 0 : select_lut(z, dj - 1, lut) + 1;
     const int nd = runlen(a, sd);
     kd = nd - n + 1;
-    h0 = (-C.t) * C.sq[n * (nd + 1)];
+    h0 = (-C.t) * gmem(C.sq)[n * (nd + 1)];
     return ins_one(del_bit(a, s), sd > s ? sd - 1 : sd);
 }
 
@@ -156,7 +156,7 @@ template <class T> __device__ __forceinline__ double mom_diag_modes(const ModelC
         zz = zz & ~one_at<T>(zp);
         const int n = zp - prev - 1;
         prev = zp;
-        kin = kin + C.eps[j] * (double)n;
+        kin = kin + gmem(C.eps)[j] * (double)n;
         sq += n * n;
     }
     const i64 N = C.N;
@@ -229,7 +229,7 @@ __device__ __forceinline__ T mom_move_to(const ModelConst &C, T a, T z, int sp, 
     const int A = np * (nq - (p == q ? 1 : 0));
     const int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
     const int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);
-    h = (C.coef * (double)cc) * (C.sq[A] * C.sq[B]);
+    h = (C.coef * (double)cc) * (gmem(C.sq)[A] * gmem(C.sq)[B]);
     // remove one boson at the start of runs q and p (higher first), then add
     // one at the start of runs r and s, whose starts moved down by one for
     // each removal from a lower mode (higher insertion first)

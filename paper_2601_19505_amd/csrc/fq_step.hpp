@@ -166,17 +166,17 @@ template <> __device__ __forceinline__ void store_rec<1>(int rec, char *base, i6
         x.x = (u32)d;
         x.y = (u32)vb;
         x.z = (u32)(vb >> 32);
-        *(uint3 *)(base + 12 * i) = x;
+        *gmem((uint3 *)(base + 12 * i)) = x;
     } else {
         ulonglong2 x;
         x.x = d;
         x.y = vb;
-        *((ulonglong2 *)base + i) = x;
+        *gmem((ulonglong2 *)base + i) = x;
     }
 }
 template <> __device__ __forceinline__ void store_rec<2>(int, char *base, i64 i, U128 d, double v)
 {
-    Rec<2> *r = (Rec<2> *)base + i;
+    FQ_GAS Rec<2> *r = gmem((Rec<2> *)base + i);
     r->a0 = d.lo;
     r->a1 = d.hi;
     r->v = v;
@@ -186,18 +186,18 @@ template <> __device__ __forceinline__ void load_rec<1>(int rec, const char *bas
 {
     a1 = 0;
     if (rec == 12) {
-        const uint3 x = *(const uint3 *)(base + 12 * i);
+        const uint3 x = *gmem((const uint3 *)(base + 12 * i));
         a0 = x.x;
         v = bitsd(((u64)x.z << 32) | x.y);
     } else {
-        const ulonglong2 x = *((const ulonglong2 *)base + i);
+        const ulonglong2 x = *gmem((const ulonglong2 *)base + i);
         a0 = x.x;
         v = bitsd(x.y);
     }
 }
 template <> __device__ __forceinline__ void load_rec<2>(int, const char *base, i64 i, u64 &a0, u64 &a1, double &v)
 {
-    const Rec<2> *r = (const Rec<2> *)base + i;
+    const FQ_GAS Rec<2> *r = gmem((const Rec<2> *)base + i);
     a0 = r->a0;
     a1 = r->a1;
     v = r->v;
@@ -381,7 +381,7 @@ template <int W, bool COUNT> struct SpawnOut {
         if (tid < G) {
             const int cg = gcnt()[tid];
             int *cn = I.two_pass ? &I.coarse_n[(tid << I.log2SUB) + sub] : &I.slab_n[out_par][tid];
-            gbase()[tid] = cg ? (i64)atomicAdd(cn, cg) : 0;
+            gbase()[tid] = cg ? (i64)gatomic_add(cn, cg) : 0;
             if (COUNT && cg) atomicAdd((unsigned long long *)&L.misc[60], (unsigned long long)cg);
         }
         __syncthreads();
@@ -487,9 +487,9 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 const u32 cw = info[2 * w + 1];
                 const u32 cnt = cw & 0x7fffffffu;
                 const i64 e = (i64)b * I.cap_t + perm[w];
-                const u64 a0 = I.tab_a[par][0][e];
-                const u64 a1 = W == 2 ? I.tab_a[par][1][e] : 0;
-                const double c = I.tab_v[par][e];
+                const u64 a0 = gmem(I.tab_a[par][0])[e];
+                const u64 a1 = W == 2 ? gmem(I.tab_a[par][1])[e] : 0;
+                const double c = gmem(I.tab_v[par])[e];
                 const T a = AddrOf<W>::make(a0, a1);
                 double h, q;
                 T dd;
@@ -502,7 +502,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                         const T st = run_starts(a);
                         int kd;
                         dd = lat_entry(I.mc, a, st, popc(st), (int)k, h, kd, lut);
-                        h = h * I.mc.gz[I.mc.N + kd];
+                        h = h * gmem(I.mc.gz)[I.mc.N + kd];
                     } else if (narrow) {
                         dd = AddrOf<W>::make((u64)mom_column_entry<u32>(I.mc, (u32)a0, (int)k, h, lut), 0);
                     } else {
@@ -528,7 +528,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                     const int m = I.mc.ndir * o;
                     int kd;
                     dd = lat_entry(I.mc, a, st, o, (int)pick(rw, (u32)m), h, kd, lut);
-                    h = h * I.mc.gz[I.mc.N + kd];
+                    h = h * gmem(I.mc.gz)[I.mc.N + kd];
                     q = (double)m / (double)cnt;
                 } else {
                     const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
@@ -660,9 +660,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             for (int e = 0; e < MT; e++) {
                 const int i = i0 + e * BS + tid;
                 if (i < nt) {
-                    t0[e] = I.tab_a[p][0][tb + i];
-                    t1[e] = W == 2 ? I.tab_a[p][1][tb + i] : 0;
-                    tc[e] = I.tab_v[p][tb + i];
+                    t0[e] = gmem(I.tab_a[p][0])[tb + i];
+                    t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
+                    tc[e] = gmem(I.tab_v[p])[tb + i];
                 }
             }
 #pragma unroll
@@ -751,11 +751,11 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         {
             const int r_beg = I.ref_off[b], r_end = I.ref_off[b + 1];
             for (int e = r_beg + tid; e < r_end; e += BS) {
-                u64 a0 = I.ref_a[0][e];
-                u64 a1 = W == 2 ? I.ref_a[1][e] : 0;
+                u64 a0 = gmem(I.ref_a[0])[e];
+                u64 a1 = W == 2 ? gmem(I.ref_a[1])[e] : 0;
                 int s = lds_find<W>(L, a0, a1, slot_hash(a0, W == 2 ? a1 : 0ull));
                 double cv = s >= 0 ? bitsd(L.lo[s]) : 0.0;
-                double term = I.yref * (I.ref_h[e] * cv);
+                double term = I.yref * (gmem(I.ref_h)[e] * cv);
                 u64 lo, hi;
                 int ovf = 0;
                 to_fixed(term, lo, hi, ovf);
@@ -796,9 +796,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 #pragma unroll
         for (int k = 0; k < 8; k++) {
             if (k < spt && rc[k] != 0.0) {
-                I.tab_a[out_par][0][ob + w] = r0[k];
-                if (W == 2) I.tab_a[out_par][1][ob + w] = r1[k];
-                I.tab_v[out_par][ob + w] = rc[k];
+                gmem(I.tab_a[out_par][0])[ob + w] = r0[k];
+                if (W == 2) gmem(I.tab_a[out_par][1])[ob + w] = r1[k];
+                gmem(I.tab_v[out_par])[ob + w] = rc[k];
                 w++;
             }
         }
@@ -875,10 +875,10 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
     int n_ex = 0, bad = 0;
     for (int i = i0; i < i1; i++) {
-        const T a = AddrOf<W>::make(I.tab_a[par][0][tb + i], W == 2 ? I.tab_a[par][1][tb + i] : 0);
+        const T a = AddrOf<W>::make(gmem(I.tab_a[par][0])[tb + i], W == 2 ? gmem(I.tab_a[par][1])[tb + i] : 0);
         u32 cnt;
         bool ex;
-        spawn_info<W, MODEL>(I, a, I.tab_v[par][tb + i], cnt, ex, bad);
+        spawn_info<W, MODEL>(I, a, gmem(I.tab_v[par])[tb + i], cnt, ex, bad);
         info[2 * i] = cnt | (ex ? 0x80000000u : 0u);
         n_ex += ex ? 1 : 0;
     }
@@ -979,7 +979,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
         __syncthreads();
         if (tid < F) {
             const int c = cnt[tid];
-            base[tid] = c ? (i64)atomicAdd(&I.slab_n[q][(g << log2F) + tid], c) : 0;
+            base[tid] = c ? (i64)gatomic_add(&I.slab_n[q][(g << log2F) + tid], c) : 0;
         }
         __syncthreads();
 #pragma unroll
