@@ -35,17 +35,6 @@ using namespace fq;
 // its instance and bucket through `map` (entry = instance << 14 | bucket);
 // without a map there is one instance and workgroup b takes bucket b.
 
-// Kernels never write a descriptor, so a workgroup reads its descriptor in
-// the constant address space: scalar loads, loaded once rather than again
-// after every store the kernel makes, and the pointers it holds are known to
-// address device memory (global, not flat, loads and stores).  The integer
-// round trip keeps the compiler from folding the cast away.
-typedef const __attribute__((address_space(4))) Inst ConstInst;
-__device__ __forceinline__ const Inst &const_inst(const Inst *p)
-{
-    return *(const Inst *)(ConstInst *)(uintptr_t)p;
-}
-
 __device__ __forceinline__ const Inst &locate(const Inst *const *insts, const u32 *map, int &b)
 {
     if (map) {

@@ -179,7 +179,7 @@ template <int BS> __device__ __forceinline__ Fx3 block_sum_fx3(Fx3 x, Fx3 *tmp)
 // workgroup (A, b): partial sums of bucket b for the pairs (A, B), B > A
 template <int W, int BS> __device__ void overlap_bucket(const Overlap &O, const int A, const int b, char *smem)
 {
-    const Inst &IA = *O.rep[A];
+    const Inst &IA = const_inst(O.rep[A]);
     const int slots = IA.slots;
     Lds L;
     L.k0 = (u64 *)smem;
@@ -214,7 +214,7 @@ template <int W, int BS> __device__ void overlap_bucket(const Overlap &O, const 
     if (s_flag && tid == 0) atomicOr(&O.flags[0], 1);
     int inexact = 0, ovf = 0;
     for (int Bi = A + 1; Bi < O.R; Bi++) {
-        const Inst &IB = *O.rep[Bi];
+        const Inst &IB = const_inst(O.rep[Bi]);
         const int pB = IB.ctrl->parity;
         const i64 nB = min((i64)IB.tab_n[pB][b], IB.cap_t);
         const i64 bb = (i64)b * IB.cap_t;
@@ -310,7 +310,7 @@ template <int W> __device__ __forceinline__ size_t gs_lds_bytes(int slots)
 template <int W, int BS> __device__ void gs_dot(const Spectral &S, const int j, const int k, const int b, char *smem)
 {
     if (gs_idle(S, j, k)) return;
-    const Inst &IJ = *S.rep[j], &IK = *S.rep[k];
+    const Inst &IJ = const_inst(S.rep[j]), &IK = const_inst(S.rep[k]);
     const int slots = 2 * IJ.slots;  // a projected run may hold the union of two buckets
     Lds L = gs_lds<W>(smem, slots);
     double *val = (double *)(smem + sizeof(u64) * slots);
@@ -378,7 +378,7 @@ template <int BS> __device__ void gs_alpha(const Spectral &S, const int j, const
 template <int W, int BS> __device__ void gs_update(const Spectral &S, const int j, const int k, const int b, char *smem)
 {
     if (gs_idle(S, j, k)) return;
-    const Inst &IJ = *S.rep[j], &IK = *S.rep[k];
+    const Inst &IJ = const_inst(S.rep[j]), &IK = const_inst(S.rep[k]);
     const int slots = 2 * IK.slots;  // the union of two buckets
     Lds L = gs_lds<W>(smem, slots);
     double *val = (double *)(smem + sizeof(u64) * slots);

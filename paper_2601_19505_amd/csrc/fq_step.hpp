@@ -108,6 +108,17 @@ struct Inst {
     int *coarse_n;
 };
 
+// Kernels never write a descriptor, so a workgroup reads its descriptor in
+// the constant address space: scalar loads, loaded once rather than again
+// after every store the kernel makes, and the pointers it holds are known to
+// address device memory (global, not flat, loads and stores).  The integer
+// round trip keeps the compiler from folding the cast away.
+typedef const __attribute__((address_space(4))) Inst ConstInst;
+__device__ __forceinline__ const Inst &const_inst(const Inst *p)
+{
+    return *(const Inst *)(ConstInst *)(uintptr_t)p;
+}
+
 __device__ __forceinline__ void set_error(Ctrl *c, int code, int bucket)
 {
     if (atomicCAS(&c->error, 0, code) == 0) c->err_bucket = bucket;
@@ -318,6 +329,64 @@ template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Ins
     if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); return; }
     lds_acc128(&L.lo[s], &L.hi[s], lo, hi);
     (void)sizeof(T);
+}
+
+// Insert NB values of this thread at once (one-word keys): the fixed-point
+// conversions first, then every first-probe compare-and-swap, then every
+// accumulator add, so the LDS round trips of the NB inserts overlap instead
+// of running one after another.  ok[e] selects the values to insert.  Sums
+// are exact, so the order of the adds does not matter.
+template <int W, int NB>
+__device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64 *a0, const u64 *a1,
+                                          const double *v, const bool *ok, int b, int &np)
+{
+    if (W != 1) {
+#pragma unroll
+        for (int e = 0; e < NB; e++)
+            if (ok[e]) lds_add<W>(L, I, a0[e], a1[e], v[e], b, np);
+        return;
+    }
+    u64 lo[NB], hi[NB], old[NB];
+    int s[NB];
+    bool go[NB];
+#pragma unroll
+    for (int e = 0; e < NB; e++) {
+        go[e] = ok[e];
+        lo[e] = hi[e] = 0;
+        if (go[e]) {
+            int ovf = 0;
+            to_fixed(v[e], lo[e], hi[e], ovf);
+            if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); go[e] = false; }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NB; e++) {
+        s[e] = 0;
+        old[e] = EMPTY;
+        if (go[e]) {
+            s[e] = (int)(slot_hash(a0[e], 0ull) & (u64)L.mask);
+            np++;
+            old[e] = atomicCAS((unsigned long long *)&L.k0[s[e]], EMPTY, a0[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NB; e++) {
+        if (go[e] && old[e] != EMPTY && old[e] != a0[e]) {
+            // collision: continue the linear probe from the next slot
+            s[e] = lds_slot<W>(L, a0[e], 0ull, (u64)(s[e] + 1), np);
+            if (s[e] < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); go[e] = false; }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < NB; e++)
+        if (go[e]) old[e] = atomicAdd((unsigned long long *)&L.lo[s[e]], (unsigned long long)lo[e]);
+#pragma unroll
+    for (int e = 0; e < NB; e++) {
+        if (go[e]) {
+            const u64 h = hi[e] + ((old[e] + lo[e]) < old[e] ? 1ull : 0ull);
+            if (h) atomicAdd((unsigned long long *)&L.hi[s[e]], (unsigned long long)h);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- spawn info
@@ -570,7 +639,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
 #define FQ_MERGE_MT 2  // table entries in flight per merge thread
 #endif
 #ifndef FQ_MERGE_MS
-#define FQ_MERGE_MS 4  // spawn records in flight per merge thread
+#define FQ_MERGE_MS 2  // spawn records in flight per merge thread (and per batch of LDS inserts)
 #endif
 
 // Merge of bucket b for step n+1: the diagonal survivors of table[p] and the
@@ -665,9 +734,13 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     tc[e] = gmem(I.tab_v[p])[tb + i];
                 }
             }
+            double tw[MT];
+            bool tok[MT];
 #pragma unroll
             for (int e = 0; e < MT; e++) {
                 const int i = i0 + e * BS + tid;
+                tw[e] = 0.0;
+                tok[e] = false;
                 if (i < nt) {
                     const T a = AddrOf<W>::make(t0[e], t1[e]);
                     double hii;
@@ -678,17 +751,18 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     double w = tc[e] * g;
                     if (EARLY && fabs(w) < I.theta)
                         w = compress1(w, I.theta, draw(I.seed, t0[e], t1[e], (u32)(n + 1), 2u, 0u).x);
-                    if (w != 0.0) lds_add<W>(L, I, t0[e], t1[e], w, b, nprobe);
+                    tw[e] = w;
+                    tok[e] = w != 0.0;
                 }
             }
+            lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe);
         }
         if (timing) { __syncthreads(); mark(1); }
         for (int i0 = 0; i0 < ns; i0 += MS * BS) {
+            bool xok[MS];
 #pragma unroll
-            for (int e = 0; e < MS; e++) {
-                const int i = i0 + e * BS + tid;
-                if (i < ns) lds_add<W>(L, I, x0[e], x1[e], xv[e], b, nprobe);
-            }
+            for (int e = 0; e < MS; e++) xok[e] = i0 + e * BS + tid < ns;
+            lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe);
             // next batch
 #pragma unroll
             for (int e = 0; e < MS; e++) {
@@ -938,27 +1012,37 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
 // ---------------------------------------------------------------- partition
 
 // Second pass of the spawn partition: workgroup cs reads coarse sub-slab cs
-// (group g = cs >> log2SUB) and splits it into the B/G buckets of the group in
-// rounds of RPT records per thread (LDS ranks, one reservation per bucket and
-// round, stores into the reserved runs).  Releases the coarse sub-slab.
+// (group g = cs >> log2SUB) and splits it into the F = B/G <= 256 buckets of
+// the group in rounds of RPT records per thread.  Each round takes ranks
+// inside the destination buckets from LDS counters, reserves one run per
+// bucket with one global atomic, and sorts the round's records by bucket in
+// LDS, so that consecutive lanes store consecutive records of one run (whole
+// cache lines instead of one scattered record per lane).  Releases the
+// coarse sub-slab.
 template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I, const int cs)
 {
-    typedef typename AddrOf<W>::T T;
+    static_assert(BS >= 256 && BS % 64 == 0, "the scan of the F <= 256 counts needs 256 threads");
+    constexpr int NRND = BS * RPT;  // records per round
     __shared__ int s_err;
-    __shared__ int cnt[256];
-    __shared__ i64 base[256];
+    __shared__ int cnt[256];        // per bucket of the group: count, then run start in the sorted round
+    __shared__ int wsum[4];
+    __shared__ i64 off[256];        // reserved run start minus the run start in the sorted round
+    __shared__ u64 st_a0[NRND];
+    __shared__ u64 st_a1[W == 2 ? NRND : 1];
+    __shared__ double st_v[NRND];
+    __shared__ unsigned char st_d[NRND];
     Ctrl *ctrl = I.ctrl;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) s_err = halted(ctrl);
     __syncthreads();
     if (s_err) return;
     const int q = ctrl->spawn_par;
     const int g = cs >> I.log2SUB;
     const int log2F = I.log2B - I.log2G;
-    const int F = 1 << log2F;
+    const int F = 1 << log2F;  // <= 256 (B <= 16384)
     const int n = min(I.coarse_n[cs], (int)I.cap_c);
     const char *src = I.coarse + (i64)cs * I.cap_c * (i64)I.rec;
-    for (int r0 = 0; r0 < n; r0 += BS * RPT) {
+    for (int r0 = 0; r0 < n; r0 += NRND) {
         if (tid < F) cnt[tid] = 0;
         __syncthreads();
         u64 a0[RPT], a1[RPT];
@@ -977,18 +1061,43 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
         for (int e = 0; e < RPT; e++)
             if (lb[e] >= 0) rk[e] = atomicAdd(&cnt[lb[e]], 1);
         __syncthreads();
+        // exclusive scan of the F counts (threads 0 .. F-1, at most four waves)
+        const int c = tid < F ? cnt[tid] : 0;
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63 && wid < 4) wsum[wid] = x;
+        __syncthreads();
         if (tid < F) {
-            const int c = cnt[tid];
-            base[tid] = c ? (i64)gatomic_add(&I.slab_n[q][(g << log2F) + tid], c) : 0;
+            int st = x - c;
+            for (int w = 0; w < wid; w++) st += wsum[w];
+            const i64 b0 = c ? (i64)gatomic_add(&I.slab_n[q][(g << log2F) + tid], c) : 0;
+            off[tid] = b0 - st;
+            cnt[tid] = st;
         }
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < RPT; e++) {
             if (lb[e] < 0) continue;
-            const i64 pos = base[lb[e]] + rk[e];
-            const i64 d = ((i64)g << log2F) + lb[e];
-            if (pos < I.cap_s) store_rec<W>(I.rec, I.slab[q], d * I.cap_s + pos, AddrOf<W>::make(a0[e], a1[e]), v[e]);
-            else set_error(ctrl, FQE_CAP_SLAB, (int)d);
+            const int j = cnt[lb[e]] + rk[e];
+            st_a0[j] = a0[e];
+            if (W == 2) st_a1[W == 2 ? j : 0] = a1[e];
+            st_v[j] = v[e];
+            st_d[j] = (unsigned char)lb[e];
+        }
+        __syncthreads();
+        const int nr = min(NRND, n - r0);
+        for (int j = tid; j < nr; j += BS) {
+            const int d = st_d[j];
+            const i64 pos = off[d] + j;
+            const i64 dg = ((i64)g << log2F) + d;
+            if (pos < I.cap_s)
+                store_rec<W>(I.rec, I.slab[q], dg * I.cap_s + pos,
+                             AddrOf<W>::make(st_a0[j], W == 2 ? st_a1[W == 2 ? j : 0] : 0ull), st_v[j]);
+            else set_error(ctrl, FQE_CAP_SLAB, (int)dg);
         }
         __syncthreads();
     }
