@@ -67,7 +67,10 @@ __global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u3
 }
 
 // one workgroup per instance
-constexpr int FIN_BS = 256;  // threads of the finalize workgroup
+#ifndef FQ_FIN_BS
+#define FQ_FIN_BS 256
+#endif
+constexpr int FIN_BS = FQ_FIN_BS;  // threads of the finalize workgroup
 __global__ __launch_bounds__(FIN_BS) void k_finalize(const Inst *const *insts)
 {
     finalize_instance<FIN_BS>(const_inst(insts[blockIdx.x]));

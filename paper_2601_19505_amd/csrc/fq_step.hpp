@@ -331,21 +331,19 @@ template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Ins
     (void)sizeof(T);
 }
 
-// Insert NB values of this thread at once (one-word keys): the fixed-point
-// conversions first, then every first-probe compare-and-swap, then every
-// accumulator add, so the LDS round trips of the NB inserts overlap instead
-// of running one after another.  ok[e] selects the values to insert.  Sums
-// are exact, so the order of the adds does not matter.
+// Insert NB values of this thread at once: the fixed-point conversions
+// first, then every first-probe compare-and-swap, then every accumulator
+// add, so the LDS round trips of the NB inserts overlap instead of running
+// one after another.  ok[e] selects the values to insert.  Sums are exact,
+// so the order of the adds does not matter.  One-word keys: the CAS is on
+// the key itself.  Two-word keys: the CAS claims the slot's state word
+// (0 -> 1); the claiming lane then writes the key and publishes the slot
+// (state 2) before any lane continues a probe, so a lane that found the
+// slot busy finds it full when it looks again.
 template <int W, int NB>
 __device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64 *a0, const u64 *a1,
                                           const double *v, const bool *ok, int b, int &np)
 {
-    if (W != 1) {
-#pragma unroll
-        for (int e = 0; e < NB; e++)
-            if (ok[e]) lds_add<W>(L, I, a0[e], a1[e], v[e], b, np);
-        return;
-    }
     u64 lo[NB], hi[NB], old[NB];
     int s[NB];
     bool go[NB];
@@ -359,22 +357,59 @@ __device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64
             if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); go[e] = false; }
         }
     }
+    if (W == 1) {
 #pragma unroll
-    for (int e = 0; e < NB; e++) {
-        s[e] = 0;
-        old[e] = EMPTY;
-        if (go[e]) {
-            s[e] = (int)(slot_hash(a0[e], 0ull) & (u64)L.mask);
-            np++;
-            old[e] = atomicCAS((unsigned long long *)&L.k0[s[e]], EMPTY, a0[e]);
+        for (int e = 0; e < NB; e++) {
+            s[e] = 0;
+            old[e] = EMPTY;
+            if (go[e]) {
+                s[e] = (int)(slot_hash(a0[e], 0ull) & (u64)L.mask);
+                np++;
+                old[e] = atomicCAS((unsigned long long *)&L.k0[s[e]], EMPTY, a0[e]);
+            }
         }
-    }
 #pragma unroll
-    for (int e = 0; e < NB; e++) {
-        if (go[e] && old[e] != EMPTY && old[e] != a0[e]) {
-            // collision: continue the linear probe from the next slot
-            s[e] = lds_slot<W>(L, a0[e], 0ull, (u64)(s[e] + 1), np);
-            if (s[e] < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); go[e] = false; }
+        for (int e = 0; e < NB; e++) {
+            if (go[e] && old[e] != EMPTY && old[e] != a0[e]) {
+                // collision: continue the linear probe from the next slot
+                s[e] = lds_slot<W>(L, a0[e], 0ull, (u64)(s[e] + 1), np);
+                if (s[e] < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); go[e] = false; }
+            }
+        }
+    } else {
+        u32 st[NB];
+        bool claimed[NB];
+#pragma unroll
+        for (int e = 0; e < NB; e++) {
+            s[e] = 0;
+            st[e] = 0u;
+            claimed[e] = false;
+            if (go[e]) {
+                s[e] = (int)(slot_hash(a0[e], a1[e]) & (u64)L.mask);
+                np++;
+                claimed[e] = __hip_atomic_compare_exchange_strong(&L.state[s[e]], &st[e], 1u, __ATOMIC_ACQUIRE,
+                                                                  __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NB; e++) {
+            if (go[e] && claimed[e]) {
+                L.k0[s[e]] = a0[e];
+                L.k1[s[e]] = a1[e];
+                __hip_atomic_store(&L.state[s[e]], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NB; e++) {
+            if (go[e] && !claimed[e]) {
+                // full with another key: probe on from the next slot; busy:
+                // look at this slot again (its key is being written)
+                const bool hit = st[e] == 2u && L.k0[s[e]] == a0[e] && L.k1[s[e]] == a1[e];
+                if (!hit) {
+                    s[e] = lds_slot<W>(L, a0[e], a1[e], (u64)(s[e] + (st[e] == 2u ? 1 : 0)), np);
+                    if (s[e] < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); go[e] = false; }
+                }
+            }
         }
     }
 #pragma unroll
