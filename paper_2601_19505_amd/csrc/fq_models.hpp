@@ -148,6 +148,10 @@ __device__ __forceinline__ T lat_entry(const ModelConst &C, T a, T st, int o, in
 // occupied modes in ascending order bit for bit.
 template <class T> __device__ __forceinline__ double mom_diag_modes(const ModelConst &C, T a)
 {
+    // eps is a host table no kernel writes, and mode j is the same for every
+    // lane: read it in the constant address space (scalar loads)
+    const __attribute__((address_space(4))) double *eps =
+        (const __attribute__((address_space(4))) double *)(uintptr_t)C.eps;
     T zz = (~a & mask_below<T>(C.nb)) | one_at<T>(C.nb);  // separators, then the end
     double kin = 0.0;
     int sq = 0, prev = -1;
@@ -156,7 +160,7 @@ template <class T> __device__ __forceinline__ double mom_diag_modes(const ModelC
         zz = zz & ~one_at<T>(zp);
         const int n = zp - prev - 1;
         prev = zp;
-        kin = kin + gmem(C.eps)[j] * (double)n;
+        kin = kin + eps[j] * (double)n;
         sq += n * n;
     }
     const i64 N = C.N;
