@@ -733,6 +733,35 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     {
         // ------------------------------------------------ 1. merge
         int nprobe = 0;
+        const int nt = I.tab_n[p][b];
+        const i64 tb = (i64)b * I.cap_t;
+        const int ns = min(I.slab_n[p][b], (int)I.cap_s);
+        const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)I.rec;
+        // Loads in flight per thread: the first MT table entries and the
+        // first MS spawn records are requested before the LDS hash is
+        // cleared, so their latency overlaps the clearing, and each later
+        // batch is requested while the current one is inserted.
+        constexpr int MT = FQ_MERGE_MT, MS = FQ_MERGE_MS;
+        u64 x0[MS], x1[MS];
+        double xv[MS];
+#pragma unroll
+        for (int e = 0; e < MS; e++) {
+            const int i = e * BS + tid;
+            if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
+        }
+        u64 t0[MT], t1[MT];
+        double tc[MT];
+#pragma unroll
+        for (int e = 0; e < MT; e++) {
+            const int i = e * BS + tid;
+            t0[e] = t1[e] = 0;
+            tc[e] = 0.0;
+            if (i < nt) {
+                t0[e] = gmem(I.tab_a[p][0])[tb + i];
+                t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
+                tc[e] = gmem(I.tab_v[p])[tb + i];
+            }
+        }
         for (int s = tid; s < slots; s += BS) {
             L.k0[s] = EMPTY;
             if (W == 2) { L.k1[s] = EMPTY; L.state[s] = 0u; }
@@ -742,33 +771,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         if (tid < 64) L.misc[tid] = 0;
         __syncthreads();
         mark(0);
-        const int nt = I.tab_n[p][b];
-        const i64 tb = (i64)b * I.cap_t;
-        const int ns = min(I.slab_n[p][b], (int)I.cap_s);
-        const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)I.rec;
-        // Loads in flight per thread: the first MT table entries and the
-        // first MS spawn records are requested before any insert, so the
-        // record loads overlap the diagonal computations of the table phase.
-        constexpr int MT = FQ_MERGE_MT, MS = FQ_MERGE_MS;
-        u64 x0[MS], x1[MS];
-        double xv[MS];
-#pragma unroll
-        for (int e = 0; e < MS; e++) {
-            const int i = e * BS + tid;
-            if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
-        }
         for (int i0 = 0; i0 < nt; i0 += MT * BS) {
-            u64 t0[MT], t1[MT];
-            double tc[MT];
-#pragma unroll
-            for (int e = 0; e < MT; e++) {
-                const int i = i0 + e * BS + tid;
-                if (i < nt) {
-                    t0[e] = gmem(I.tab_a[p][0])[tb + i];
-                    t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
-                    tc[e] = gmem(I.tab_v[p])[tb + i];
-                }
-            }
             double tw[MT];
             bool tok[MT];
 #pragma unroll
@@ -791,6 +794,16 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                 }
             }
             lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe);
+            // next batch
+#pragma unroll
+            for (int e = 0; e < MT; e++) {
+                const int i = i0 + (MT + e) * BS + tid;
+                if (i < nt) {
+                    t0[e] = gmem(I.tab_a[p][0])[tb + i];
+                    t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
+                    tc[e] = gmem(I.tab_v[p])[tb + i];
+                }
+            }
         }
         if (timing) { __syncthreads(); mark(1); }
         for (int i0 = 0; i0 < ns; i0 += MS * BS) {
