@@ -738,7 +738,13 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
         if (rc) { col_free(&c); return rc; }
         double ac = fabs(val[i]);
         if (is_exact(ac, P->t_rel, c.n)) nrec += c.n;
-        else if (ceil(ac) > 1073741824.0) { col_free(&c); return ORC_EINVAL; }
+        /* the block index of a draw has 28 bits (tag << 28 | block): at most
+         * 2^28 blocks of 4 words, i.e. 2^29 momentum-space attempts (two
+         * words each) or 2^30 attempts of the other models (one word) */
+        else if (ceil(ac) > (H->model == ORC_MOM1D ? 536870912.0 : 1073741824.0)) {
+            col_free(&c);
+            return ORC_EINVAL;
+        }
         else nrec += (int64_t)ceil(ac);
         col_free(&c);
     }
