@@ -3,18 +3,27 @@
 Default workload (the configuration the headline metric is quoted on):
 momentum-space 1D Bose-Hubbard, M = N = 16, u = 4, t = 1, dtau = 5e-4,
 target 1e8 walkers, FP64 amplitudes, seed 2, start from the k = 0 condensate
-with 10 walkers.  `--warmup` steps grow the population to the target (not
-timed), then exactly `--steps` steps are timed between two
-torch.cuda.synchronize() calls.
+with 10 walkers.
+
+Schedule (the paper likewise equilibrates before it times, Sec. 7.2):
+  1. ramp, untimed: steps until ||c||_1 first reaches N_t, then 500 more
+     steps so that the shift has settled (`ramp_steps` in the output);
+  2. `--warmup` untimed steps;
+  3. exactly `--steps` steps timed between two torch.cuda.synchronize()
+     calls.
+No headline value is printed when the mean ||c||_1 of the timed steps is
+below 0.9 N_t.
 
 value = walker-steps/s = sum over the timed steps of ||c^(n)||_1 / wall time.
 A step is four launches: merge, spawn, spawn partition, shift update.  The
-roofline object prices the slower of the merge and spawn kernels by its
-algorithmic HBM bytes (merge of step k: read c^(k-1) and the spawn records of
-step k, write c^(k); spawn: read c^(k), write the spawn records of step k+1;
-16 bytes per entry or record for one address word) over its mean launch time
-measured with HIP events on the stream it runs on.  The CPU oracle is timed
-on a bounded sample of the same steady-state vector.
+`roofline` object prices the dominant kernel by its algorithmic HBM bytes
+(merge of step k: read c^(k-1) and the spawn records of step k, write c^(k);
+spawn: read c^(k), write the spawn records of step k+1; 8 W + 8 bytes per
+entry or record) over its mean launch time measured with HIP events on the
+stream it runs on; `roofline.step` prices the whole step the same way,
+(8 W + 8) (L_n + 2 S_n + L_(n+1)) bytes per step over the wall time.  The CPU
+oracle is timed on a bounded sample of the same steady-state vector, on one
+core and as independent processes on every core the run may use.
 
 Prints one JSON line.
 """
@@ -37,16 +46,16 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "c3": dict(cfg="c3", name="mom1d_M16_N16_u4_dtau5e-4_Nt1e8",
                table_capacity=19_500_000, spawn_capacity=200_000_000, buckets=16384,
-               lds_slots=2048, block=512, spawn_block=256, warmup=3000, steps=1000),
+               lds_slots=2048, block=512, spawn_block=256, steps=1000),
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
                table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=16384,
-               lds_slots=2048, block=512, spawn_block=256, warmup=6000, steps=1000),
+               lds_slots=2048, block=512, spawn_block=256, steps=1000),
     "c2d": dict(cfg="c2d", name="real2d_6x6_N36_u1_t0.1_g1_dtau1e-2_Nt1e7_W2",
                 table_capacity=30_000_000, spawn_capacity=60_000_000, buckets=16384,
-                lds_slots=2048, block=512, spawn_block=256, warmup=3000, steps=2000),
+                lds_slots=2048, block=512, spawn_block=256, steps=2000),
     "c1": dict(cfg="c1", name="real1d_M6_N6_u6_dtau1e-3_Nt1e3",
                table_capacity=1024, spawn_capacity=8192, buckets=0, lds_slots=0, block=0,
-               spawn_block=0, warmup=0, steps=10_000),
+               spawn_block=0, steps=10_000),
 }
 
 
@@ -120,36 +129,99 @@ def make_solver(fq, wl, cfg, **over):
     return fq.Solver(cfg["model"], cfg["M"], cfg["N"], **kw)
 
 
-def cpu_baseline(state, cfg, step_index, shift, budget_s=15.0):
-    """Time the oracle's step on a bounded sample of the steady-state vector."""
+def _oracle_step_time(cfg, addrs, vals, shift, step_index, order, k):
+    """One oracle step over the entries order[:k]: (seconds, walkers, entries)."""
     import oracle
-    addrs, vals = state
-    n = len(vals)
-    rng = np.random.default_rng(123)
-    order = rng.permutation(n)
     P = oracle.params(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], dtau=cfg["dtau"],
                       target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"],
                       lx=cfg.get("lx", 0), g=cfg.get("g", 0.0))
+    n = len(vals)
     a2 = np.zeros((n, 2), np.uint64)
     a2[:, :addrs.shape[1]] = addrs
     ref = a2[int(np.argmax(np.abs(vals)))]
-    k = min(n, 2000)
+    idx = order[:k]
+    t0 = time.perf_counter()
+    oracle.step(P, a2[idx], vals[idx], shift, step_index, ref, 10.0,
+                cap=64 * (k + int(np.abs(vals[idx]).sum())) + 1024)
+    return time.perf_counter() - t0, float(np.abs(vals[idx]).sum()), k
+
+
+def _cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return dict(cpu_model=model, nproc=usable, cpu_count=os.cpu_count())
+
+
+# worker processes of the all-cores figure: at most this many (the CPU share
+# of one GPU on a shared node)
+CPU_WORKERS_MAX = 16
+
+
+def cpu_baseline(state, cfg, step_index, shift, budget_s=15.0):
+    """Time the oracle's step on a bounded sample of the steady-state vector:
+    on one host core, and as independent processes on every usable core
+    (each on its own random sample of the same size), summed."""
+    import subprocess
+    import tempfile
+    addrs, vals = state
+    n = len(vals)
+    order = np.random.default_rng(123).permutation(n)
+    k = min(n, 4000)
     t_used = 0.0
     while True:
-        idx = order[:k]
-        t0 = time.perf_counter()
-        oracle.step(P, a2[idx], vals[idx], shift, step_index, ref, 10.0,
-                    cap=64 * (k + int(np.abs(vals[idx]).sum())) + 1024)
-        dt = time.perf_counter() - t0
+        dt, walkers, _ = _oracle_step_time(cfg, addrs, vals, shift, step_index, order, k)
         t_used += dt
         if dt > budget_s / 3 or k == n or t_used > budget_s:
             break
         k = min(n, int(k * min(8.0, max(2.0, (budget_s / 2) / max(dt, 1e-3)))))
-    walkers = float(np.abs(vals[idx]).sum())
-    return dict(value=walkers / dt, unit="walker-steps/s", cores=1, kind="oracle",
-                sample=f"one oracle step over {k} of {n} steady-state entries "
-                       f"({walkers:.3g} walkers), {dt:.1f} s, serial C on one host core",
-                entries_per_s=k / dt)
+    info = _cpu_info()
+    out = dict(value=walkers / dt, unit="walker-steps/s", cores=1, kind="oracle",
+               sample=f"one oracle step over {k} of {n} steady-state entries "
+                      f"({walkers:.3g} walkers), {dt:.1f} s, serial C on one host core",
+               entries_per_s=k / dt, **info)
+    # all cores: independent oracle processes (no GPU use), one per usable core
+    nw = max(1, min(CPU_WORKERS_MAX, info["nproc"]))
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "state.npz")
+        np.savez(path, addrs=addrs, vals=vals)
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker", path,
+                                   cfg_key(cfg), str(step_index), repr(shift), str(1000 + i), str(k)],
+                                  stdout=subprocess.PIPE, text=True)
+                 for i in range(nw)]
+        res = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+    rates = [r["walkers"] / r["seconds"] for r in res]
+    out["all_cores"] = dict(value=float(sum(rates)), unit="walker-steps/s", processes=nw,
+                            kind="oracle",
+                            sample=f"{nw} concurrent oracle processes, each one step over its own "
+                                   f"random {k} of the {n} steady-state entries")
+    return out
+
+
+def cfg_key(cfg):
+    for k, v in synthetic.CONFIGS.items():
+        if v is cfg:
+            return k
+    raise KeyError("not a named configuration")
+
+
+def oracle_worker(path, key, step_index, shift, seed, k):
+    """Entry of one all-cores worker process: one timed oracle step."""
+    z = np.load(path)
+    addrs, vals = z["addrs"], z["vals"]
+    order = np.random.default_rng(seed).permutation(len(vals))
+    dt, walkers, k = _oracle_step_time(synthetic.CONFIGS[key], addrs, vals, shift, step_index, order, k)
+    print(json.dumps(dict(seconds=dt, walkers=walkers, entries=k)), flush=True)
 
 
 def _spec(inst, **lay):
@@ -220,7 +292,7 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
 PAPER_2D_STEPS_PER_S = 112.0  # Sec. 7.2: one CPU node, 32 threads, N_t = 1e7
 
 
-def bench_lattice(fq, torch, warmup=2000, steps=2000):
+def bench_lattice(fq, torch, warmup=100, steps=2000, settle=500):
     """The benchmark system of Sec. 7.2 (periodic 6 x 6 lattice, N = 36,
     u = 1, t = 0.1, Gutzwiller importance sampling, N_t = 1e7): FCIQMC steps
     per second at steady state, beside the paper's CPU figure (context: a
@@ -231,14 +303,9 @@ def bench_lattice(fq, torch, warmup=2000, steps=2000):
     s = make_solver(fq, wl, cfg)
     a = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), cfg["W"])
     s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
-    t0 = time.perf_counter()
-    done = 0
-    while done < warmup:
-        k = min(1000, warmup - done)
-        st = s.run(k)
-        done += k
-        log(f"[bench] lattice warmup {done}/{warmup}: norm {st['norm'][-1]:.4g} len {st['len'][-1]} "
-            f"({time.perf_counter() - t0:.1f} s)")
+    ramp_steps, _, _, _ = ramp(s, cfg["target"], settle, "lattice ramp", chunk=500)
+    if warmup:
+        s.run(warmup)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = s.run(steps)
@@ -246,8 +313,8 @@ def bench_lattice(fq, torch, warmup=2000, steps=2000):
     wall = time.perf_counter() - t1
     s.close()
     sps = steps / wall
-    out = dict(workload=wl["name"], model=MODEL_NAMES[cfg["model"]], warmup=warmup, steps=steps,
-               steps_per_s=sps, ms_per_step=wall / steps * 1e3,
+    out = dict(workload=wl["name"], model=MODEL_NAMES[cfg["model"]], ramp_steps=ramp_steps,
+               warmup=warmup, steps=steps, steps_per_s=sps, ms_per_step=wall / steps * 1e3,
                walker_steps_per_s=float(st["norm"].sum()) / wall,
                mean_len=float(st["len"].mean()), mean_spawns=float(st["spawns"].mean()),
                shift_mean=float(st["shift"].mean()),
@@ -259,7 +326,7 @@ def bench_lattice(fq, torch, warmup=2000, steps=2000):
     return out
 
 
-def bench_replicas(fq, torch, wl, cfg, warmup=1500, steps=300):
+def bench_replicas(fq, torch, wl, cfg, warmup=100, steps=300, settle=500):
     """Two replicas of the momentum-space workload (seeds differ) in one
     batch with the overlap c_A . c_B computed after every step on the
     device (Sec. 4.3).  The same replicas then run the same number of steps
@@ -273,13 +340,9 @@ def bench_replicas(fq, torch, wl, cfg, warmup=1500, steps=300):
     a = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), cfg["W"])
     for i in range(2):
         b.instance(i).set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
-    t0 = time.perf_counter()
-    done = 0
-    while done < warmup:
-        k = min(500, warmup - done)
-        b.run(k)
-        done += k
-        log(f"[bench] replica warmup {done}/{warmup} ({time.perf_counter() - t0:.1f} s)")
+    ramp_steps, _, _, _ = ramp(b, cfg["target"], settle, "replica ramp", chunk=500)
+    if warmup:
+        b.run(warmup)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st, ov, inexact = b.run_replicas(steps)
@@ -294,7 +357,7 @@ def bench_replicas(fq, torch, wl, cfg, warmup=1500, steps=300):
     join_bytes = float(rec * (st["len"][0] + st["len"][1]).astype(np.float64).mean())
     over_ms = (wall_o - wall_n) / steps * 1e3
     out = dict(workload=f"2 replicas of {wl['name']} (seeds {cfg['seed']}, {cfg['seed'] + 100})",
-               replicas=2, warmup=warmup, steps=steps,
+               replicas=2, ramp_steps=ramp_steps, warmup=warmup, steps=steps,
                walker_steps_per_s=float(st["norm"].sum()) / wall_o, ms_per_step=wall_o / steps * 1e3,
                ms_per_step_without_overlaps=wall_n / steps * 1e3, overlap_ms_per_step=over_ms,
                overlap_algorithmic_bytes_per_step=join_bytes,
@@ -406,11 +469,49 @@ def compression_study(fq, torch, steps=20000, skip=5000):
                 **out)
 
 
+def ramp(s, target, settle, what, chunk=250, limit=60000):
+    """Untimed ramp of a solver or batch `s`: steps until ||c||_1 first
+    reaches the target (every instance of a batch), then `settle` more steps.
+    Returns (steps run, step count at which the target was first reached,
+    seconds, last statistics row; a batch's rows hold one entry per
+    instance)."""
+    t0 = time.perf_counter()
+    done, reached, last = 0, None, None
+    while reached is None:
+        if done >= limit:
+            raise RuntimeError(f"{what}: ||c||_1 did not reach {target:.3g} in {limit} steps")
+        st = s.run(chunk)
+        norm = st["norm"] if st.ndim == 1 else st["norm"].min(axis=0)
+        hit = np.nonzero(norm >= target)[0]
+        if len(hit):
+            reached = done + int(hit[0]) + 1
+        done += chunk
+        last = st[..., -1]
+        log(f"[bench] {what} {done}: norm {np.min(last['norm']):.4g} len {np.max(last['len'])} "
+            f"({time.perf_counter() - t0:.1f} s)")
+    rest = reached + settle - done
+    while rest > 0:
+        k = min(chunk, rest)
+        last = s.run(k)[..., -1]
+        done += k
+        rest -= k
+    log(f"[bench] {what}: target reached at step {reached}, {done} ramp steps "
+        f"({time.perf_counter() - t0:.1f} s)")
+    return done, reached, time.perf_counter() - t0, last
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
+        p, key, stp, shift, seed, k = sys.argv[2:8]
+        oracle_worker(p, key, int(stp), float(shift), int(seed), int(k))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps after the ramp (default 100)")
+    ap.add_argument("--settle", type=int, default=500,
+                    help="ramp steps after ||c||_1 first reaches N_t")
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -453,7 +554,7 @@ def main():
             wl[k_wl] = getattr(args, k_arg)
     cfg = synthetic.CONFIGS[wl["cfg"]]
     steps = wl["steps"] if args.steps is None else args.steps
-    warmup = wl["warmup"] if args.warmup is None else args.warmup
+    warmup = 100 if args.warmup is None else args.warmup
     torch.cuda.set_device(0)
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib * 2**20 // 8
@@ -469,18 +570,12 @@ def main():
     a = fq.encode(occ, cfg["W"])
     s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
     log(f"[bench] workload {wl['name']}: layout buckets={s.layout.buckets} "
-        f"slots={s.layout.lds_slots} block={s.layout.block} spawn_block={s.layout.spawn_block} workspace={s.nbytes / 2**30:.2f} GiB")
-    t0 = time.perf_counter()
-    done = 0
-    warm = []
-    while done < warmup:
-        k = min(500, warmup - done)
-        st = s.run(k)
-        warm.append(st)
-        done += k
-        log(f"[bench] warmup {done}/{warmup}: norm {st['norm'][-1]:.4g} len {st['len'][-1]} "
-            f"shift {st['shift'][-1]:.4f} ({time.perf_counter() - t0:.1f} s)")
-    prev = warm[-1][-1] if warm else None
+        f"slots={s.layout.lds_slots} block={s.layout.block} spawn_block={s.layout.spawn_block} "
+        f"workspace={s.nbytes / 2**30:.2f} GiB")
+    ramp_steps, first_reach, ramp_s, prev = ramp(s, cfg["target"], args.settle, "ramp")
+    if warmup:
+        prev = s.run(warmup)[-1]
+    log(f"[bench] warmup {warmup} steps after the ramp: norm {prev['norm']:.4g} len {prev['len']}")
     torch.cuda.synchronize()
     s.set_timing(True)
     s.kernel_time(reset=True)
@@ -499,6 +594,8 @@ def main():
     log(f"[bench] timed {steps} steps in {wall:.3f} s; norm {st['norm'][-1]:.4g} len {st['len'][-1]}; "
         f"kernel ms/step " + ", ".join(f"{k} {v / max(nl, 1):.3f}" for k, v in kms.items()))
     walker_steps = float(st["norm"].sum())
+    mean_norm = float(st["norm"].mean())
+    valid = mean_norm >= 0.9 * cfg["target"]
     value = walker_steps / wall
     # spawns of the step after the timed region (written by the last timed spawn launch)
     nxt_last = float(s.run(1)["spawns"][-1])
@@ -506,7 +603,7 @@ def main():
     # records of step k and writes c^(k); spawn k reads c^(k) and writes the
     # spawn records of step k+1
     rec = 8 * cfg["W"] + 8
-    lens = np.concatenate([[prev["len"] if prev is not None else 1], st["len"]]).astype(np.float64)
+    lens = np.concatenate([[prev["len"]], st["len"]]).astype(np.float64)
     spw = st["spawns"].astype(np.float64)
     nxt = np.concatenate([spw[1:], [nxt_last]])
     per_kernel = {
@@ -516,23 +613,32 @@ def main():
     kern = {}
     for k, b in per_kernel.items():
         t_s = kms[k] / 1e3 / max(nl, 1)
-        kern[k] = {"mean_ms": t_s * 1e3, "algorithmic_bytes": b, "achieved_GBs": b / t_s / 1e9}
+        kern[k] = {"mean_ms": t_s * 1e3, "algorithmic_bytes": b, "achieved_GBs": b / t_s / 1e9,
+                   "frac": b / t_s / 1e9 / HBM_PEAK_GBS}
     kern["partition"] = {"mean_ms": kms["partition"] / max(nl, 1),
                          "algorithmic_bytes": float(2 * rec * nxt.mean())}
     kern["partition"]["achieved_GBs"] = (kern["partition"]["algorithmic_bytes"] /
                                          max(kern["partition"]["mean_ms"], 1e-9) / 1e6)
     kern["finalize"] = {"mean_ms": kms["finalize"] / max(nl, 1)}
-    if args.workload == "c3":
-        for k in ("merge", "spawn"):
+    for k in ("merge", "spawn", "partition"):
+        tr = measured_traffic(fq, "k_" + ("part" if k == "partition" else k)) if args.workload == "c3" else None
+        kern[k]["traffic"] = tr
+        if k in ("merge", "spawn") and args.workload == "c3":
             vi = measured_valu(fq, "k_" + k)
             if vi is not None:
                 kern[k]["valu_insts_per_launch"] = vi
                 kern[k]["valu_issue_frac"] = vi / (kern[k]["mean_ms"] * 1e-3) / VALU_ISSUE_PEAK
     dom = max(per_kernel, key=lambda k: kern[k]["mean_ms"])
     achieved = kern[dom]["achieved_GBs"]
+    # the whole step: (8 W + 8) (L_n + 2 S_n + L_(n+1)) bytes over the wall time
+    step_bytes = rec * (lens[:-1] + 2.0 * spw + lens[1:])
+    step_gbs = float(step_bytes.sum()) / wall / 1e9
+    traffic_step = None
+    if all(kern[k].get("traffic") is not None for k in ("merge", "spawn", "partition")):
+        traffic_step = sum(kern[k]["traffic"] for k in ("merge", "spawn", "partition"))
     out = {
         "metric": "FCIQMC walker-steps/s at 1e8 walkers",
-        "value": value,
+        "value": value if valid else None,
         "unit": "walker-steps/s",
         "n_gpus": 1,
         "steps": steps,
@@ -549,18 +655,28 @@ def main():
                    "addr_words": cfg["W"], "buckets": s.layout.buckets,
                    "lds_slots": s.layout.lds_slots, "block": s.layout.block,
                    "spawn_block": s.layout.spawn_block,
-                   "mean_norm": float(st["norm"].mean()), "mean_len": float(st["len"].mean()),
+                   "mean_norm": mean_norm, "mean_len": float(st["len"].mean()),
                    "mean_spawns": float(st["spawns"].mean())},
+        "ramp": {"steps": ramp_steps, "first_reach_step": first_reach, "settle_steps": args.settle,
+                 "seconds": ramp_s,
+                 "rule": "untimed: steps until ||c||_1 first reaches N_t, then the settle steps; "
+                         "--warmup and --steps count after it"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(fq, "k_" + dom) if args.workload == "c3" else None,
+                     "traffic": kern[dom]["traffic"],
                      "kernel": "k_" + dom, "mean_kernel_ms": kern[dom]["mean_ms"],
-                     "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"]},
+                     "algorithmic_bytes_per_launch": kern[dom]["algorithmic_bytes"],
+                     "step": {"achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS,
+                              "algorithmic_bytes_per_step": float(step_bytes.mean()),
+                              "traffic_per_step": traffic_step}},
         "kernels": kern,
         "entry_steps_per_s": float(st["len"].sum()) / wall,
         "spawns_per_s": float(st["spawns"].sum()) / wall,
         "shift_mean": float(st["shift"].mean()),
     }
+    if not valid:
+        out["error"] = (f"timed mean ||c||_1 {mean_norm:.4g} is below 0.9 N_t: not the stated "
+                        f"configuration, no headline value")
     state = s.get_state() if not args.no_cpu_baseline else None
     s.close()
     del s
@@ -569,7 +685,7 @@ def main():
         out["lattice_2d"] = bench_lattice(fq, torch)
         torch.cuda.empty_cache()
     if not args.no_replicas and args.workload == "c3":
-        out["replicas"] = bench_replicas(fq, torch, wl, cfg, warmup=args.batch_warmup)
+        out["replicas"] = bench_replicas(fq, torch, wl, cfg)
         torch.cuda.empty_cache()
     if not args.no_batch:
         out["batched"] = bench_batched(fq, torch, warmup=args.batch_warmup, steps=args.batch_steps)

@@ -106,6 +106,14 @@ typedef struct {
  * parent) -- instead of to the sums (late compression, the default).
  * Contributions compressed to 0 are not spawn events. */
 #define FQ_FLAG_EARLY_COMPRESSION 32
+/* Stability check of dtau (Sec. 3.1, the projector is stable for
+ * dtau < 2 / (E_max - E_0)).  Creation fails with FQ_EINVAL unless
+ * dtau * Wb < 2, where Wb = |u| N (N - 1) / 2 + 2 z |t| N (z = 2 on the ring
+ * and in momentum space, 4 on the square lattice) bounds E_max - E_0 from
+ * above (Weyl's inequality for the hopping and interaction terms).  This
+ * flag skips the check, for callers who know their walkers never reach the
+ * high-energy states the bound guards against. */
+#define FQ_FLAG_UNCHECKED_DTAU 64
 /* Sampled dumps: with FQ_FLAG_DUMP_SAMPLE(k), k in 1..20, the dumps keep only
  * the spawn events whose destination, and the merged amplitudes whose
  * address, fall in a fixed sample of about 2^-k of all addresses (bits
@@ -129,10 +137,21 @@ typedef struct {
  * `step` n, `len` = number of stored addresses of c^(n), `exact_steps` and
  * `inexact_steps` = parents of c^(n-1) spawned exactly / stochastically,
  * `spawns` = spawn events of step n, `shift` = S^(n), `norm` = ||c^(n)||_1,
- * `hproj` = y^T H c^(n), `vproj` = y^T c^(n). */
+ * `hproj` = y^T H c^(n), `vproj` = y^T c^(n), `flags` = FQ_ROW_* bits.
+ *
+ * FQ_ROW_INEXACT: some sum of this step (annihilation, ||c||_1, y^T H c,
+ * y^T c, or the norm of a state set just before) was not the exactly
+ * rounded sum of its terms.  Sums are exact integer sums of the terms on a
+ * grid of 2^-80; a term that is not a multiple of 2^-80 (possible only for
+ * |term| < 2^-27) is first rounded to the nearest grid point, an error of at
+ * most 2^-81 per term.  With the flag clear, every sum of the row is exactly
+ * rounded.  fq_run then returns FQ_OK and fq_last_error() names the first
+ * flagged step. */
+#define FQ_ROW_INEXACT 1
 typedef struct {
     int64_t step, len, exact_steps, inexact_steps, spawns;
     double shift, norm, hproj, vproj;
+    int64_t flags;
 } fq_step_stats;
 
 /* Sizes of the device data structures.  table_capacity: largest number of

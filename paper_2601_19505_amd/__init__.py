@@ -23,6 +23,7 @@ FLAG_DUMP_SPAWNS = 1
 FLAG_DUMP_MERGED = 2
 FLAG_PHASE_TIMING = 4
 FLAG_EARLY_COMPRESSION = 32
+FLAG_UNCHECKED_DTAU = 64
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ENOMEM", -5: "EBUSY",
           -6: "EDIVERGED", -7: "ENOTFOUND"}
@@ -54,7 +55,8 @@ class Layout(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("step", C.c_int64), ("len", C.c_int64), ("exact_steps", C.c_int64),
                 ("inexact_steps", C.c_int64), ("spawns", C.c_int64), ("shift", C.c_double),
-                ("norm", C.c_double), ("hproj", C.c_double), ("vproj", C.c_double)]
+                ("norm", C.c_double), ("hproj", C.c_double), ("vproj", C.c_double),
+                ("flags", C.c_int64)]
 
 
 class ServerConfig(C.Structure):
@@ -74,7 +76,9 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 STATS_DTYPE = np.dtype([("step", np.int64), ("len", np.int64), ("exact_steps", np.int64),
                         ("inexact_steps", np.int64), ("spawns", np.int64), ("shift", np.float64),
-                        ("norm", np.float64), ("hproj", np.float64), ("vproj", np.float64)])
+                        ("norm", np.float64), ("hproj", np.float64), ("vproj", np.float64),
+                        ("flags", np.int64)])
+ROW_INEXACT = 1  # FQ_ROW_INEXACT: some sum of the row's step was not exactly rounded
 assert STATS_DTYPE.itemsize == C.sizeof(StepStats)
 
 _lib = None
@@ -269,6 +273,12 @@ class Solver:
             err.stats = out
             raise err
         return out
+
+    def last_error(self):
+        """fq_last_error() of this handle (also notes inexact sums after a
+        successful run)."""
+        msg = lib().fq_last_error(self.h)
+        return msg.decode() if msg else ""
 
     def get_state(self, cap=None):
         """Current state (addresses, values, shift, step); order unspecified."""

@@ -7,7 +7,8 @@
 //    a signed 128-bit fixed-point integer with 80 fractional bits and summed
 //    with integer adds (LDS or global atomics); the total is rounded once to
 //    the nearest double.  For |contribution| >= 2^-28 and |sum| < 2^46 this
-//    is the exactly rounded sum, identical for every order of summation.
+//    is the exactly rounded sum, identical for every order of summation;
+//    a contribution that is not a multiple of 2^-80 is reported (inexact).
 //  * Bit operations on the unary Fock address of Sec. 6.1 (N+M-1 bits, mode 1
 //    in the low bits) held in one or two 64-bit words.
 //  * The two Hamiltonians: the real-space ring of Sec. 2 (Eq.
@@ -237,9 +238,11 @@ __device__ __forceinline__ u32 pick(u32 r, u32 m) { return (u32)(((u64)r * (u64)
 
 constexpr int FIX_FRAC = 80;  // fractional bits of the fixed-point accumulators
 
-// double -> two's complement 128-bit round(v * 2^80) (half-even).  Sets *ovf
-// when |v| >= 2^46 or v is not finite.
-__device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf)
+// double -> two's complement 128-bit round(v * 2^80) (half-even).  Sets ovf
+// when |v| >= 2^46 or v is not finite, and inx when the value is not a
+// multiple of 2^-80 (it was rounded; only possible for |v| < 2^-27), so that
+// a sum of such values is no longer the exactly rounded sum.
+__device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf, int &inx)
 {
     u64 b = dbits(v);
     int e = (int)((b >> 52) & 0x7ff);
@@ -255,9 +258,12 @@ __device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf)
         else { L = m << sh; H = m >> (64 - sh); }
     } else {
         int s = -sh;
-        if (s > 53) { L = 0; }
-        else {
+        if (s > 53) {
+            L = 0;
+            inx |= m != 0 ? 1 : 0;
+        } else {
             u64 q = m >> s, rem = m & ((1ull << s) - 1), half = 1ull << (s - 1);
+            inx |= rem != 0 ? 1 : 0;
             if (rem > half || (rem == half && (q & 1ull))) q++;
             L = q;
         }
@@ -266,6 +272,11 @@ __device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf)
     if (b >> 63) { L = ~L + 1; H = ~H + (L == 0 ? 1 : 0); }
     lo = L;
     hi = H;
+}
+__device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf)
+{
+    int inx = 0;
+    to_fixed(v, lo, hi, ovf, inx);
 }
 
 // two's complement 128-bit fixed point -> nearest double (half-even)

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(256) void k_insert(const Inst *Ip, const u64 *sa, c
     if (threadIdx.x == 0) acc[0] = acc[1] = 0;
     __syncthreads();
     u64 nlo = 0, nhi = 0;
+    int inx = 0;
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
         u64 a0 = sa[i * W], a1 = W == 2 ? sa[i * W + 1] : 0;
         double v = sv[i];
@@ -176,10 +177,11 @@ __global__ __launch_bounds__(256) void k_insert(const Inst *Ip, const u64 *sa, c
         I.tab_v[p][o] = v;
         u64 lo, hi;
         int ovf = 0;
-        to_fixed(fabs(v), lo, hi, ovf);
+        to_fixed(fabs(v), lo, hi, ovf, inx);
         if (ovf) set_error(ctrl, FQE_DIVERGED, (int)b);
         add128(nlo, nhi, lo, hi);
     }
+    if (inx) atomicOr(&ctrl->inexact_in, 1u);
     if (nlo | nhi) lds_acc128(&acc[0], &acc[1], nlo, nhi);
     __syncthreads();
     if (threadIdx.x == 0 && (acc[0] | acc[1])) glb_acc128(ctrl->acc_norm, acc[0], acc[1]);
@@ -343,6 +345,7 @@ size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048 +
 
 constexpr size_t LDS_MAX = 160 * 1024;
 static_assert(sizeof(Ctrl) % 4 == 0, "Ctrl is copied in 32-bit words");
+static_assert(sizeof(StepStats) == sizeof(fq_step_stats), "StepStats mirrors fq_step_stats");
 
 // A set of instances stepped together: one launch per kernel per step.
 struct Exec {
@@ -367,6 +370,20 @@ struct Resolved {
     int nsq;
 };
 
+// Upper bound on the spectral width E_max - E_0 of the Hamiltonian, from
+// Weyl's inequality applied to H = T + V: the hopping term T of N bosons has
+// its spectrum in [-z t N, z t N] (the one-boson hopping matrix has z
+// entries of size t per row, z = 2 on the ring, 4 on the square lattice;
+// momentum space is the ring in another basis), and V = (u/2) sum n(n-1) has
+// its spectrum between 0 and (u/2) N (N - 1).  Importance sampling is a
+// similarity transformation and keeps the spectrum.
+double spectral_width_bound(const fq_hamiltonian *h)
+{
+    const double z = h->model == FQ_REAL2D ? 4.0 : 2.0;
+    const double N = h->N;
+    return std::fabs(h->u) * 0.5 * N * (N - 1.0) + 2.0 * z * std::fabs(h->t) * N;
+}
+
 int validate(const fq_hamiltonian *h, const fq_params *p, std::string &err)
 {
     if (!h || !p) { err = "null argument"; return FQ_EINVAL; }
@@ -385,11 +402,23 @@ int validate(const fq_hamiltonian *h, const fq_params *p, std::string &err)
     int nb = h->N + h->M - 1;
     if (nb > (p->addr_words == 1 ? 62 : 126)) { err = "N+M-1 too large for addr_words"; return FQ_EINVAL; }
     if (!(p->dtau > 0) || !(p->target_walkers > 0) || !(p->threshold > 0) || !(p->t_rel >= 0) ||
-        !(p->zeta >= 0) || !(p->xi >= 0) || !std::isfinite(p->dtau)) {
-        err = "dtau, target_walkers, threshold must be > 0; t_rel, zeta, xi >= 0";
+        !(p->zeta >= 0) || !(p->xi >= 0) || !std::isfinite(p->dtau) || !std::isfinite(p->target_walkers) ||
+        !std::isfinite(p->threshold) || !std::isfinite(p->zeta) || !std::isfinite(p->xi)) {
+        err = "dtau, target_walkers, threshold must be finite and > 0; t_rel >= 0; zeta, xi finite and >= 0";
         return FQ_EINVAL;
     }
     if (!std::isfinite(h->t) || !std::isfinite(h->u)) { err = "t and u must be finite"; return FQ_EINVAL; }
+    // Stability of the projector (Sec. 3.1): dtau < 2 / (E_max - E_0).
+    const double width = spectral_width_bound(h);
+    if (!(p->flags & FQ_FLAG_UNCHECKED_DTAU) && !(p->dtau * width < 2.0)) {
+        char msg[200];
+        snprintf(msg, sizeof msg,
+                 "dtau = %.6g violates the stability bound dtau < 2 / (E_max - E_0) = %.6g (spectral width "
+                 "at most %.6g); FQ_FLAG_UNCHECKED_DTAU skips this check",
+                 p->dtau, 2.0 / width, width);
+        err = msg;
+        return FQ_EINVAL;
+    }
     return FQ_OK;
 }
 
@@ -654,6 +683,15 @@ static int read_ctrl(fq_handle *q, Ctrl &c, hipStream_t s);
 static int load_state(fq_handle *q, const u64 *sa, const double *sv, i64 n, double shift, i64 step,
                       const uint64_t *ref_addr, double ref_val, hipStream_t s);
 
+// text of fq_last_error after a successful run in which some sum was not
+// exactly rounded (its rows carry FQ_ROW_INEXACT)
+static std::string inexact_note(i64 step)
+{
+    return "note: from step " + std::to_string(step) +
+           " on, some sums were not exactly rounded: a contribution below 2^-27 was rounded to a "
+           "multiple of 2^-80 (rows flagged FQ_ROW_INEXACT)";
+}
+
 static const char *fqe_name(int e)
 {
     switch (e) {
@@ -661,7 +699,7 @@ static const char *fqe_name(int e)
     case FQE_CAP_SLAB: return "spawn slab capacity exceeded";
     case FQE_CAP_LDS: return "LDS hash of a bucket is full (use more buckets or lds_slots)";
     case FQE_DIVERGED: return "walker number diverged or became non-finite";
-    case FQE_ATTEMPTS: return "more than 2^30 spawn attempts from one address";
+    case FQE_ATTEMPTS: return "too many spawn attempts from one address (more than 2^29 in momentum space, 2^30 otherwise)";
     case FQE_BARRIER: return "grid barrier timed out";
     default: return "unknown device error";
     }
@@ -707,7 +745,7 @@ int fq_workspace_size(const fq_hamiltonian *h, const fq_params *p, const fq_layo
     fq_layout L;
     std::string err;
     int rc = resolve(h, p, layout, R, L, err);
-    if (rc) return rc;
+    if (rc) { g_err = err; return rc; }
     if (bytes) *bytes = R.total;
     if (layout_out) *layout_out = L;
     return FQ_OK;
@@ -1105,6 +1143,7 @@ int fq_run(fq_handle *q, int64_t n_steps, fq_step_stats *stats_out, void *stream
             return fqe_status(c.error);
         }
         if (completed != chunk) { q->err = "step count mismatch"; return FQ_EHIP; }
+        if (c.first_inexact) q->err = inexact_note(c.first_inexact);
     }
     return FQ_OK;
 }

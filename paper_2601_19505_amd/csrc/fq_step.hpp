@@ -40,7 +40,9 @@ enum { FQE_CAP_TABLE = 1, FQE_CAP_SLAB = 2, FQE_CAP_LDS = 3, FQE_DIVERGED = 4, F
 struct StepStats {  // mirrors fq_step_stats
     i64 step, len, exact_steps, inexact_steps, spawns;
     double shift, norm, hproj, vproj;
+    i64 flags;
 };
+constexpr i64 ROW_INEXACT = 1;  // FQ_ROW_INEXACT
 
 struct Ctrl {
     i64 step;          // index n of the current state c^(n)
@@ -48,7 +50,7 @@ struct Ctrl {
     int error;         // 0 or an FQE_* code
     double shift;      // S^(n)
     double norm;       // ||c^(n)||_1
-    u32 pad1;
+    u32 inexact_in;    // the norm of a state being set was rounded (reported in the next row)
     u32 max_load;      // largest LDS hash occupancy seen
     i64 ring_base;     // step number stored in ring row 0
     u64 acc_norm[2];   // norm of a state being set (set_state only)
@@ -58,6 +60,7 @@ struct Ctrl {
     u64 phase[10];     // summed wall-clock ticks per phase (opt-in diagnostics)
     u64 probes;        // LDS hash probes summed over all inserts (diagnostics)
     u64 inserts;
+    i64 first_inexact; // first step whose row has ROW_INEXACT since the state was set, 0 if none
 };
 
 // per-bucket partial statistics, written with plain stores by the workgroup
@@ -65,7 +68,7 @@ struct Ctrl {
 // atomics on the step's critical path)
 struct Part {
     u64 norm[2], hproj[2], vproj[2];
-    i64 len, load;
+    i64 len, load, inexact;
 };
 struct SpawnPart {
     i64 exact, inexact, spawns, pad;
@@ -316,21 +319,6 @@ __device__ __forceinline__ u64 slot_hash(u64 a0, u64 a1)
     return (u64)x;
 }
 
-template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Inst &I, u64 a0, u64 a1,
-                                                        double v, int b, int &np)
-{
-    typedef typename AddrOf<W>::T T;
-    u64 h = slot_hash(a0, W == 2 ? a1 : 0ull);
-    int s = lds_slot<W>(L, a0, a1, h, np);
-    if (s < 0) { set_error(I.ctrl, FQE_CAP_LDS, b); return; }
-    u64 lo, hi;
-    int ovf = 0;
-    to_fixed(v, lo, hi, ovf);
-    if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); return; }
-    lds_acc128(&L.lo[s], &L.hi[s], lo, hi);
-    (void)sizeof(T);
-}
-
 // Insert NB values of this thread at once: the fixed-point conversions
 // first, then every first-probe compare-and-swap, then every accumulator
 // add, so the LDS round trips of the NB inserts overlap instead of running
@@ -342,7 +330,7 @@ template <int W> __device__ __forceinline__ void lds_add(const Lds &L, const Ins
 // slot busy finds it full when it looks again.
 template <int W, int NB>
 __device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64 *a0, const u64 *a1,
-                                          const double *v, const bool *ok, int b, int &np)
+                                          const double *v, const bool *ok, int b, int &np, int &inx)
 {
     u64 lo[NB], hi[NB], old[NB];
     int s[NB];
@@ -353,7 +341,7 @@ __device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64
         lo[e] = hi[e] = 0;
         if (go[e]) {
             int ovf = 0;
-            to_fixed(v[e], lo[e], hi[e], ovf);
+            to_fixed(v[e], lo[e], hi[e], ovf, inx);
             if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); go[e] = false; }
         }
     }
@@ -440,8 +428,10 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
     if (exact) {
         cnt = (u32)m;
     } else {
+        // the 28-bit block index of the draw counter allows 2^28 blocks: two
+        // momentum-space attempts per block, four of the other models
         double n = ceil(ac);
-        if (!(n <= 1073741824.0)) { bad = 1; n = 0.0; }
+        if (!(n <= (MODEL == 1 || MODEL == 2 ? 536870912.0 : 1073741824.0))) { bad = 1; n = 0.0; }
         cnt = (u32)n;
     }
 }
@@ -730,6 +720,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     for (int k = 0; k < 8; k++) { r0[k] = 0; r1[k] = 0; rc[k] = 0.0; }
 
     int used = 0;  // occupied LDS slots of this thread
+    int inx = 0;   // some contribution of this thread was rounded to the fixed-point grid
     {
         // ------------------------------------------------ 1. merge
         int nprobe = 0;
@@ -793,7 +784,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     tok[e] = w != 0.0;
                 }
             }
-            lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe);
+            lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe, inx);
             // next batch
 #pragma unroll
             for (int e = 0; e < MT; e++) {
@@ -810,7 +801,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             bool xok[MS];
 #pragma unroll
             for (int e = 0; e < MS; e++) xok[e] = i0 + e * BS + tid < ns;
-            lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe);
+            lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe, inx);
             // next batch
 #pragma unroll
             for (int e = 0; e < MS; e++) {
@@ -865,8 +856,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         for (int k = 0; k < 8; k++)
             if (k < spt) L.lo[tid * spt + k] = dbits(rc[k]);
         mark(3);
-        // 128-bit accumulators: [40,41] norm, [42,43] y.Hc, [44,45] y.c
-        if (tid < 6) L.misc[40 + tid] = 0;
+        // 128-bit accumulators: [40,41] norm, [42,43] y.Hc, [44,45] y.c;
+        // [46] inexact flag of the bucket
+        if (tid < 7) L.misc[40 + tid] = 0;
         __syncthreads();
 
         // ------------------------------------------------ 3. projected energy
@@ -880,10 +872,10 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                 double term = I.yref * (gmem(I.ref_h)[e] * cv);
                 u64 lo, hi;
                 int ovf = 0;
-                to_fixed(term, lo, hi, ovf);
+                to_fixed(term, lo, hi, ovf, inx);
                 lds_acc128((u64 *)&L.misc[42], (u64 *)&L.misc[43], lo, hi);
                 if (e == I.ref_self) {
-                    to_fixed(I.yref * cv, lo, hi, ovf);
+                    to_fixed(I.yref * cv, lo, hi, ovf, inx);
                     lds_acc128((u64 *)&L.misc[44], (u64 *)&L.misc[45], lo, hi);
                 }
             }
@@ -899,7 +891,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             mine++;
             u64 lo, hi;
             int ovf = 0;
-            to_fixed(fabs(rc[k]), lo, hi, ovf);
+            to_fixed(fabs(rc[k]), lo, hi, ovf, inx);
             add128(nlo, nhi, lo, hi);
         }
     }
@@ -933,6 +925,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         add128(nlo, nhi, x, y);
     }
     if ((tid & 63) == 0 && (nlo | nhi)) lds_acc128((u64 *)&L.misc[40], (u64 *)&L.misc[41], nlo, nhi);
+    if (__any(inx) && (tid & 63) == 0) atomicOr((unsigned long long *)&L.misc[46], 1ull);
     __syncthreads();
     if (tid == 0) {
         I.tab_n[out_par][b] = (int)total;
@@ -945,6 +938,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         pt.vproj[1] = (u64)L.misc[45];
         pt.len = total;
         pt.load = occupied;
+        pt.inexact = L.misc[46];
         I.part[b] = pt;
     }
     mark(4);
@@ -1160,7 +1154,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
 // depend on the number of buckets.
 template <int BS> __device__ void finalize_instance(const Inst &I)
 {
-    __shared__ u64 red[BS / 64][12];
+    __shared__ u64 red[BS / 64][12];  // the 12th word: inexact flags
     __shared__ int s_err;
     Ctrl *ctrl = I.ctrl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -1171,7 +1165,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
     const int p = ctrl->parity;
     const double S = ctrl->shift;
     u64 nl = 0, nh = 0, hl = 0, hh = 0, vl = 0, vh = 0;
-    i64 len = 0, load = 0, ex = 0, in = 0, sp = 0;
+    i64 len = 0, load = 0, ex = 0, in = 0, sp = 0, inx = 0;
     const SpawnPart *spp = I.spart[(n + 1) & 1];
     for (int b = tid; b < I.B; b += BS) {
         const Part pt = I.part[b];
@@ -1180,6 +1174,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
         add128(vl, vh, pt.vproj[0], pt.vproj[1]);
         len += pt.len;
         load = max(load, pt.load);
+        inx |= pt.inexact;
         const SpawnPart q = spp[b];
         ex += q.exact;
         in += q.inexact;
@@ -1195,6 +1190,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
         add128(vl, vh, x, y);
         len += __shfl_down(len, o, 64);
         load = max(load, (i64)__shfl_down(load, o, 64));
+        inx |= __shfl_down(inx, o, 64);
         ex += __shfl_down(ex, o, 64);
         in += __shfl_down(in, o, 64);
         sp += __shfl_down(sp, o, 64);
@@ -1202,7 +1198,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
     if (lane == 0) {
         red[wid][0] = nl; red[wid][1] = nh; red[wid][2] = hl; red[wid][3] = hh;
         red[wid][4] = vl; red[wid][5] = vh; red[wid][6] = (u64)len; red[wid][7] = (u64)load;
-        red[wid][8] = (u64)ex; red[wid][9] = (u64)in; red[wid][10] = (u64)sp;
+        red[wid][8] = (u64)ex; red[wid][9] = (u64)in; red[wid][10] = (u64)sp; red[wid][11] = (u64)inx;
     }
     __syncthreads();
     if (tid == 0) {
@@ -1215,6 +1211,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
             ex += (i64)red[w][8];
             in += (i64)red[w][9];
             sp += (i64)red[w][10];
+            inx |= (i64)red[w][11];
         }
         const double N1 = from_fixed(nl, nh);
         const double hp = from_fixed(hl, hh);
@@ -1226,6 +1223,7 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
             S1 = (S - za * det_log(N1 / N0)) - xb * det_log(N1 / I.target);
         }
         if ((u32)load > ctrl->max_load) ctrl->max_load = (u32)load;
+        inx |= ctrl->inexact_in ? 1 : 0;
         if (!(N1 < 17592186044416.0) || !(S1 == S1)) {
             set_error(ctrl, FQE_DIVERGED, -1);
             s_err = 1;
@@ -1242,9 +1240,12 @@ template <int BS> __device__ void finalize_instance(const Inst &I)
                 R.norm = N1;
                 R.hproj = hp;
                 R.vproj = vp;
+                R.flags = inx ? ROW_INEXACT : 0;
             }
             ctrl->shift = S1;
             ctrl->norm = N1;
+            ctrl->inexact_in = 0;
+            if (inx && ctrl->first_inexact == 0) ctrl->first_inexact = n + 1;
             ctrl->step = n + 1;
             ctrl->parity = 1 - p;
         }

@@ -17,7 +17,8 @@ Workloads (all t = 1, threshold 1, 1D periodic Bose-Hubbard):
   u uniform in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7];
 * the benchmark system of Sec. 7.2: the periodic 6 x 6 square lattice with
   N = 36, u = 1, t = 0.1, Gutzwiller importance sampling (g = 1, reading),
-  dtau = 0.01 (reading), N_t = 1e7, 71-bit (W = 2) addresses, seed 3; and a
+  dtau = 1.5e-3 (reading: half the stability bound 2 / (E_max - E_0) of
+  Sec. 3.1, about 3.0e-3 here), N_t = 1e7, 71-bit (W = 2) addresses, seed 3; and a
   3 x 2 lattice with N = 6 and the same couplings at N_t = 1e3, small enough
   for exact diagonalisation.
 """
@@ -36,7 +37,7 @@ CONFIGS = {
                seed=1, W=2, theta=1.0),
     "c3": dict(model=MOM1D, M=16, N=16, t=1.0, u=4.0, dtau=5e-4, target=1e8, steps=5_000,
                seed=2, W=1, theta=1.0),
-    "c2d": dict(model=REAL2D, M=36, N=36, lx=6, t=0.1, u=1.0, g=1.0, dtau=1e-2, target=1e7,
+    "c2d": dict(model=REAL2D, M=36, N=36, lx=6, t=0.1, u=1.0, g=1.0, dtau=1.5e-3, target=1e7,
                 steps=50_000, seed=3, W=2, theta=1.0),
     "c2d_small": dict(model=REAL2D, M=6, N=6, lx=3, t=0.1, u=1.0, g=1.0, dtau=1e-2, target=1e3,
                       steps=10_000, seed=0, W=1, theta=1.0),

@@ -46,9 +46,10 @@ def test_encode_rejects_overflow():
         fq.encode([40, 40], 1)
 
 
-def _ws(model=0, M=6, N=6, W=1, lx=0, g=0.0, **kw):
-    h = fq.Hamiltonian(model, M, N, lx, 1.0, 6.0, g)
-    p = fq.Params(1e-3, 1e3, 0.08, 0.0016, 1.0, 1.0, 0, W, 0)
+def _ws(model=0, M=6, N=6, W=1, lx=0, g=0.0, t=1.0, u=6.0, dtau=1e-3, target=1e3, theta=1.0,
+        flags=0, **kw):
+    h = fq.Hamiltonian(model, M, N, lx, t, u, g)
+    p = fq.Params(dtau, target, 0.08, 0.0016, theta, 1.0, 0, W, flags)
     lay = fq.Layout(kw.get("table", 1000), kw.get("spawn", 4000), kw.get("buckets", 0),
                     kw.get("slots", 0), kw.get("block", 0), kw.get("spawn_block", 0))
     return fq.workspace_size(h, p, lay)
@@ -69,7 +70,9 @@ def test_workspace_size_and_defaults():
                                 dict(buckets=3), dict(spawn_block=128), dict(spawn_block=2048),
                                 dict(model=2, M=9, lx=1), dict(model=2, M=10, lx=3),
                                 dict(model=2, M=6, lx=6), dict(model=1, M=8, g=0.1),
-                                dict(g=float("nan")), dict(model=2, M=36, N=36, lx=6, W=1)])
+                                dict(g=float("nan")), dict(model=2, M=36, N=36, lx=6, W=1, u=1.0),
+                                dict(target=float("inf")), dict(target=0.0), dict(theta=float("nan")),
+                                dict(theta=0.0), dict(dtau=0.0), dict(dtau=float("inf"))])
 def test_workspace_size_rejects_invalid(kw):
     with pytest.raises(fq.FqError):
         _ws(**kw)
@@ -77,7 +80,7 @@ def test_workspace_size_rejects_invalid(kw):
 
 def test_lattice_workspace_sizes():
     """The 6 x 6 lattice with 36 bosons needs two address words (71 bits)."""
-    n, lay = _ws(model=2, M=36, N=36, lx=6, W=2, g=1.0, table=1000, spawn=4000)
+    n, lay = _ws(model=2, M=36, N=36, lx=6, W=2, g=1.0, t=0.1, u=1.0, table=1000, spawn=4000)
     assert n > 0
     n1, _ = _ws(model=0, M=6, N=6, g=0.5)
     assert n1 > 0
@@ -101,3 +104,43 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def _width_bound(model, N, t, u):
+    z = 4.0 if model == 2 else 2.0
+    return abs(u) * 0.5 * N * (N - 1) + 2.0 * z * abs(t) * N
+
+
+@pytest.mark.parametrize("model,M,N,lx,t,u,g", [
+    (0, 6, 6, 0, 1.0, 6.0, 0.0),      # the 6/6 ring of the accuracy examples
+    (1, 16, 16, 0, 1.0, 4.0, 0.0),    # the momentum-space benchmark
+    (2, 36, 36, 6, 0.1, 1.0, 1.0),    # the 6 x 6 lattice of the performance benchmarks
+    (0, 12, 12, 0, 1.0, 6.0, 0.0),
+    (0, 20, 20, 0, 1.0, -2.0, 0.3),   # attractive interaction, importance sampling
+])
+def test_dtau_stability_bound(model, M, N, lx, t, u, g):
+    """dtau is checked against the stability bound of Sec. 3.1, dtau <
+    2 / (E_max - E_0), with E_max - E_0 bounded by |u| N (N-1)/2 + 2 z |t| N:
+    just below the bound is accepted, just above rejected, and the unchecked
+    flag accepts it."""
+    W = 2 if N + M - 1 > 62 else 1
+    lim = 2.0 / _width_bound(model, N, t, u)
+    kw = dict(model=model, M=M, N=N, lx=lx, t=t, u=u, g=g, W=W)
+    assert _ws(dtau=lim * 0.999, **kw)[0] > 0
+    with pytest.raises(fq.FqError, match="stability bound"):
+        _ws(dtau=lim * 1.001, **kw)
+    assert _ws(dtau=lim * 1.001, flags=fq.FLAG_UNCHECKED_DTAU, **kw)[0] > 0
+
+
+@pytest.mark.parametrize("model,M,N,lx,t,u,g", [
+    (0, 6, 6, 0, 1.0, 6.0, 0.0), (0, 5, 7, 0, 1.0, -3.0, 0.0), (0, 2, 5, 0, 1.0, 4.0, 0.0),
+    (1, 6, 6, 0, 1.0, 6.0, 0.0), (1, 5, 4, 0, 0.5, 3.0, 0.0),
+    (2, 4, 5, 2, 1.0, 2.0, 0.2), (2, 6, 6, 3, 0.1, 1.0, 1.0), (2, 9, 4, 3, 1.0, 0.5, 0.0),
+])
+def test_width_bound_holds_against_dense_spectrum(orc, model, M, N, lx, t, u, g):
+    """The width bound the dtau check uses is an upper bound on the true
+    spectral width E_max - E_0 (dense eigenvalues of small systems; the
+    similarity transform of importance sampling keeps the spectrum)."""
+    h = orc.ham(model, M, N, t, u, lx=lx, g=g)
+    ev = np.linalg.eigvals(orc.dense_matrix(h)).real
+    assert ev.max() - ev.min() <= _width_bound(model, N, t, u) * (1 + 1e-12)

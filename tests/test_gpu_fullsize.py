@@ -3,18 +3,30 @@ times, on sampled outputs the oracle computes one by one.
 
 The vector is grown to its target (1e8 walkers for the momentum-space
 benchmark, 1e7 for the 20/20 real-space ring with two address words and for
-the 6 x 6 lattice of Sec. 7.2 with importance sampling), then
-two single steps run with sampled dumps (about 2^-k of all addresses).  For
-the sampled addresses the test checks, bit for bit:
+the 6 x 6 lattice of Sec. 7.2 with importance sampling), then two single
+steps run with sampled dumps: the dumps keep the spawn events into, and the
+merged sums of, a fixed sample of about 2^-k of all addresses (the library's
+sampling rule: bits 24 .. 24+k-1 of its address hash are zero).
 
-* every dumped spawn event (parent, attempt, destination, value) equals the
-  oracle's event regenerated from that parent, and every oracle event of
-  those parents that lands on a sampled address was dumped;
-* the merged pre-compression amplitude equals the diagonal survivor plus the
-  dumped events, summed exactly;
+The expected values come from the oracle, not from the dumps.  Every parent
+that can spawn into a sampled address lies in that address's column (the
+connectivity of the Hamiltonian is symmetric, also under importance
+sampling), so the test collects, for every sampled merged address, the
+entries of the state that lie in its column, regenerates all their spawn
+events with the oracle and checks, bit for bit:
+
+* the spawn events into sampled addresses (parent, attempt, destination,
+  value) equal the oracle's events of those parents into sampled addresses;
+  a parent whose events were lost, or an event sent elsewhere, fails;
+* each sampled merged amplitude equals the diagonal survivor plus the
+  oracle's events into it, summed exactly;
+* every entry of the state in the sample is among the merged addresses, and
+  the oracle events of a random sample of parents into sampled addresses
+  all land on merged addresses (no sampled destination is missing);
 * the compressed value follows the compression rule with the oracle's draw;
 
-and for the whole new state: len, ||c||_1 (exact sum), y.c and y.Hc.
+and for the whole new state: len, ||c||_1 (exact sum), y.c and y.Hc, with
+every sum of the step exactly rounded (no inexact flag).
 """
 import sys
 
@@ -31,33 +43,6 @@ def _flush(*a):
     sys.stdout.flush()
 
 
-def _key(a):
-    a = np.asarray(a, dtype=np.uint64).reshape(len(a), -1)
-    hi = a[:, 1] if a.shape[1] > 1 else np.zeros(len(a), np.uint64)
-    return hi, a[:, 0]
-
-
-def _index(addrs):
-    hi, lo = _key(addrs)
-    order = np.lexsort((lo, hi))
-    return hi[order], lo[order], order
-
-
-def _lookup(idx, vals, addrs):
-    """Values of `addrs` in a state (0 where absent)."""
-    shi, slo, order = idx
-    hi, lo = _key(addrs)
-    out = np.zeros(len(hi))
-    # combine the two words into one sortable key per word pair
-    pos = np.searchsorted(shi, hi, side="left")
-    for i in range(len(hi)):
-        p, q = pos[i], np.searchsorted(shi, hi[i], side="right")
-        j = p + np.searchsorted(slo[p:q], lo[i])
-        if j < q and slo[j] == lo[i]:
-            out[i] = vals[order[j]]
-    return out
-
-
 def _pad2(a):
     a = np.asarray(a, dtype=np.uint64).reshape(len(a), -1)
     if a.shape[1] == 2:
@@ -65,7 +50,60 @@ def _pad2(a):
     return np.concatenate([a, np.zeros((len(a), 1), np.uint64)], 1)
 
 
-@pytest.mark.parametrize("name,k", [("c3", 12), ("c2", 10), ("c2d", 10)])
+def _keys(a):
+    """Sortable structured keys (hi, lo) of addresses given as W words."""
+    a = _pad2(a)
+    k = np.empty(len(a), dtype=[("hi", np.uint64), ("lo", np.uint64)])
+    k["hi"], k["lo"] = a[:, 1], a[:, 0]
+    return k
+
+
+class _State:
+    """Sorted lookup over a state (addresses as W words, values)."""
+
+    def __init__(self, addrs, vals):
+        k = _keys(addrs)
+        self.order = np.argsort(k, kind="stable")
+        self.k = k[self.order]
+        self.v = np.asarray(vals)[self.order]
+
+    def find(self, addrs):
+        """Values of `addrs` (0 where absent) and a presence mask."""
+        q = _keys(addrs)
+        pos = np.searchsorted(self.k, q)
+        pos = np.minimum(pos, len(self.k) - 1)
+        hit = self.k[pos] == q
+        return np.where(hit, self.v[pos], 0.0), hit
+
+
+def _mix64(x):
+    x = x.astype(np.uint64)
+    with np.errstate(over="ignore"):
+        x = x ^ (x >> np.uint64(30))
+        x = x * np.uint64(0xBF58476D1CE4E5B9)
+        x = x ^ (x >> np.uint64(27))
+        x = x * np.uint64(0x94D049BB133111EB)
+        x = x ^ (x >> np.uint64(31))
+    return x
+
+
+def _sampled(addrs, W, k):
+    """The library's dump sample: bits 24 .. 24+k-1 of the address hash zero."""
+    a = _pad2(addrs)
+    if W == 1:
+        h = _mix64(a[:, 0])
+    else:
+        with np.errstate(over="ignore"):
+            h = _mix64(a[:, 0] ^ _mix64(a[:, 1] + np.uint64(0x9E3779B97F4A7C15)))
+    return ((h >> np.uint64(24)) & np.uint64((1 << k) - 1)) == 0
+
+
+def _tuple_keys(a):
+    a = _pad2(a)
+    return list(zip(a[:, 1].tolist(), a[:, 0].tolist()))
+
+
+@pytest.mark.parametrize("name,k", [("c3", 14), ("c2", 10), ("c2d", 12)])
 def test_full_size_sampled_step(orc, name, k):
     import bench
     import paper_2601_19505_amd as fq
@@ -76,13 +114,9 @@ def test_full_size_sampled_step(orc, name, k):
     s = bench.make_solver(fq, wl, cfg, flags=flags)
     a0 = fq.encode(synthetic.start_occupation(cfg["model"], cfg["M"], cfg["N"]), W)
     s.set_state([a0], [10.0], 0.0, 0, ref=a0, yref=10.0)
-    warm = {"c3": 1500, "c2": 3000, "c2d": 2000}[name]
-    _flush(f"[full size {name}] warmup {warm} steps, layout buckets={s.layout.buckets} "
+    _flush(f"[full size {name}] ramp to {cfg['target']:.3g} walkers, layout buckets={s.layout.buckets} "
            f"slots={s.layout.lds_slots} block={s.layout.block} spawn_block={s.layout.spawn_block}")
-    done = 0
-    while done < warm:
-        s.run(min(500, warm - done))
-        done += min(500, warm - done)
+    bench.ramp(s, cfg["target"], 100, f"full size {name}")
     cap = 4 * ((wl["spawn_capacity"] + wl["table_capacity"]) >> k) + 65536
     # step n -> n+1: the spawn dump holds the spawns of c^(n+1) for step n+2
     s.run(1)
@@ -101,44 +135,64 @@ def test_full_size_sampled_step(orc, name, k):
     P = orc.params(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], dtau=cfg["dtau"],
                    target=cfg["target"], theta=cfg["theta"], seed=cfg["seed"], lx=lx, g=g)
     h = orc.ham(cfg["model"], cfg["M"], cfg["N"], cfg["t"], cfg["u"], lx=lx, g=g)
-    par, att, dst, val = ev
-    idx1 = _index(a1)
-    # oracle events of the dumped parents
-    ukeys = {}
-    for p in _pad2(par):
-        ukeys.setdefault((int(p[1]), int(p[0])), None)
-    plist = np.array([[lo, hi] for hi, lo in ukeys], dtype=np.uint64)
-    pvals = _lookup(idx1, v1, plist if W == 2 else plist[:, :1])
-    assert np.all(pvals != 0.0)
-    cap = len(pvals) + int(np.ceil(np.abs(pvals)).sum()) + 1024  # records of these parents
-    o = orc.step(P, plist, pvals, S1, n1 + 1, plist[0], 10.0, cap=cap, events=True)
-    sampled = set(zip(*(x.tolist() for x in _key(mg[0]))))
-    want = {}
-    for e in o["events"]:
-        d = (int(e["dest"][1]), int(e["dest"][0]))
-        if d in sampled:
-            pk = (int(plist[e["parent"]][1]), int(plist[e["parent"]][0]))
-            want[(pk, int(e["attempt"]))] = (d, float(e["value"]).hex())
-    got = {}
-    for p, a_, d, v in zip(_pad2(par), att, _pad2(dst), val):
-        got[((int(p[1]), int(p[0])), int(a_))] = ((int(d[1]), int(d[0])), float(v).hex())
-    assert len(got) == len(par)
-    assert got == want
-    # merged amplitude = diagonal survivor + events, exactly summed
-    into = {}
-    for (pk, _), (d, vh) in got.items():
-        into.setdefault(d, []).append(float.fromhex(vh))
+    state1 = _State(a1, v1)
     mg_a = _pad2(mg[0])
-    surv_c = _lookup(idx1, v1, mg[0])
+    assert np.all(_sampled(mg_a, W, k))
+    merged = set(_tuple_keys(mg_a))
+    # every sampled entry of the state has its survivor among the merged addresses
+    assert set(_tuple_keys(_pad2(a1)[_sampled(a1, W, k)])) <= merged
+    # every parent of a sampled merged address: the entries of c^(n+1) in its
+    # column, and the address itself (its diagonal survivor)
+    cand = [mg_a]
+    diag = np.zeros(len(mg_a))
     for i in range(len(mg_a)):
-        key = (int(mg_a[i][1]), int(mg_a[i][0]))
+        d, dests, _ = orc.column(h, mg_a[i], cap=4096)
+        diag[i] = d
+        cand.append(dests)
+    cand = np.unique(_keys(np.concatenate(cand)))
+    cand_a = np.stack([cand["lo"], cand["hi"]], 1)
+    pv, hit = state1.find(cand_a)
+    parents, pvals = cand_a[hit], pv[hit]
+    # plus a random sample of parents, for the completeness of the sampled destinations
+    rng = np.random.default_rng(7)
+    extra = rng.choice(len(v1), size=min(len(v1), 4000), replace=False)
+    parents = np.concatenate([parents, _pad2(a1[extra])])
+    pvals = np.concatenate([pvals, v1[extra]])
+    u = np.unique(_keys(parents), return_index=True)[1]
+    parents, pvals = parents[u], pvals[u]
+    _flush(f"[full size {name}] oracle events of {len(pvals)} parents")
+    ocap = len(pvals) + int(np.ceil(np.abs(pvals)).sum()) + 1024  # records of these parents
+    o = orc.step(P, parents, pvals, S1, n1 + 1, parents[0], 10.0, cap=ocap, events=True)
+    oe = o["events"]
+    odest = _pad2(oe["dest"])
+    into_sample = _sampled(odest, W, k)
+    okeys = _tuple_keys(odest[into_sample])
+    # no sampled destination is missing from the merged dump
+    assert set(okeys) <= merged
+    pkeys = _tuple_keys(parents)
+    want = {}
+    for e, d in zip(oe[into_sample], okeys):
+        want[(pkeys[int(e["parent"])], int(e["attempt"]))] = (d, float(e["value"]).hex())
+    par, att, dst, val = ev
+    got = {}
+    for p, a_, d, v in zip(_tuple_keys(par), att, _tuple_keys(dst), val):
+        got[(p, int(a_))] = (d, float(v).hex())
+    assert len(got) == len(par)
+    # the oracle's event set covers every parent of the sampled addresses
+    # that were merged, so the two sets must agree exactly
+    assert got == want
+    # merged amplitude = diagonal survivor + the oracle's events, exactly summed
+    into = {}
+    for (_, (d, vh)) in want.items():
+        into.setdefault(d, []).append(float.fromhex(vh))
+    surv_c, _ = state1.find(mg_a)
+    for i, key in enumerate(_tuple_keys(mg_a)):
         terms = list(into.get(key, []))
         if surv_c[i] != 0.0:
-            diag = orc.column(h, mg_a[i], cap=4096)[0]
-            terms.append(surv_c[i] * (1.0 + cfg["dtau"] * (S1 - diag)))
+            terms.append(surv_c[i] * (1.0 + cfg["dtau"] * (S1 - diag[i])))
         assert float(orc.fsum(terms)).hex() == float(mg[1][i]).hex(), key
     # compression of the sampled merged amplitudes
-    new_c = _lookup(_index(a2), v2, mg[0])
+    new_c, _ = _State(a2, v2).find(mg_a)
     theta = cfg["theta"]
     for i in range(len(mg_a)):
         w = float(mg[1][i])
@@ -147,18 +201,20 @@ def test_full_size_sampled_step(orc, name, k):
         elif w == 0.0:
             exp = 0.0
         else:
-            u = int(orc.draw(cfg["seed"], mg_a[i], n2, 1, 0)[0]) * 2.0 ** -32
-            exp = (theta if w > 0 else -theta) if u * theta < abs(w) else 0.0
+            uu = int(orc.draw(cfg["seed"], mg_a[i], n2, 1, 0)[0]) * 2.0 ** -32
+            exp = (theta if w > 0 else -theta) if uu * theta < abs(w) else 0.0
         assert float(new_c[i]).hex() == float(exp).hex()
     # statistics of the whole new state
     row = st2[0]
+    assert int(row["flags"]) == 0
     assert int(row["len"]) == len(v2)
     assert float(row["norm"]).hex() == float(orc.fsum(np.abs(v2))).hex()
     ref = _pad2(np.asarray([a0]))[0]
     diag_r = orc.column(h, ref, cap=4096)[0]
     dcol, hcol = orc.row(h, ref, cap=4096)  # y.Hc takes the row of the reference
-    cref = _lookup(_index(a2), v2, np.asarray([a0]))[0]
+    state2 = _State(a2, v2)
+    cref = state2.find(np.asarray([a0]))[0][0]
     assert float(row["vproj"]).hex() == float(10.0 * cref).hex()
-    ccol = _lookup(_index(a2), v2, dcol if W == 2 else dcol[:, :1])
+    ccol, _ = state2.find(dcol)
     terms = [10.0 * (hv * cv) for hv, cv in zip(hcol, ccol)] + [10.0 * (diag_r * cref)]
     assert float(row["hproj"]).hex() == float(orc.fsum(terms)).hex()

@@ -24,11 +24,11 @@ def _flush(*a):
 
 
 def _runs(fq, R, seeds, starts, ref, M, N, u, dtau, target, W=1, buckets=0, lx=0, g=0.0, model=None,
-          table=16384, spawn=131072):
+          table=16384, spawn=131072, flags=0):
     model = fq.REAL1D if model is None else model
     specs = [dict(model=model, M=M, N=N, t=1.0, u=u, dtau=dtau, target_walkers=target, seed=s,
                   addr_words=W, table_capacity=table, spawn_capacity=spawn, buckets=buckets, lx=lx, g=g,
-                  lds_slots=2048, block=512)
+                  lds_slots=2048, block=512, flags=flags)
              for s in seeds[:R]]
     b = fq.Batch(specs)
     for i in range(R):
@@ -68,7 +68,11 @@ def test_spectral_runs_bit_exact(orc, R, W, buckets, model, M, N, u, lx, g, step
     rows, ost = orc.spectral_run(Ps, starts, a, steps)
     assert not inexact
     for r in range(R):
-        for f in st.dtype.names:
+        # the projection v_k - (alpha v_j) leaves entries far below 2^-27 where
+        # the two runs nearly cancel, so rows may carry ROW_INEXACT (their
+        # survivors are rounded to the 2^-80 grid); the rows still equal the
+        # oracle's exactly rounded sums bit for bit here
+        for f in orc.STATS_FIELDS:
             want = np.array([x[f] for x in rows[r]], dtype=st[r][f].dtype)
             assert st[r][f].tobytes() == want.tobytes(), (r, f)
         ga, gv, _, gstep = got[r]
@@ -80,14 +84,19 @@ def test_spectral_12_12_first_excited_state_printed(orc):
     """The example of Sec. 2.2: the 12/12 ring at u = 6, N_t = 1e5, 1e4
     steps, two spectral states; the paper prints S2 = -5.665 +- 0.001
     (skip 5000) against E1 = -5.66708.  The second run starts one hop from
-    the uniform state; dtau = 0.01 (the default time step, reading)."""
+    the uniform state; dtau = 0.01 (the default time step, reading).  That
+    dtau is above the stability bound 2 / (E_max - E_0) of Sec. 3.1 (the
+    width of this spectrum is about 400), as in the paper's own run: walkers
+    never reach the high-energy states, so the run is stable in practice and
+    the check is skipped with FLAG_UNCHECKED_DTAU."""
     import paper_2601_19505_amd as fq
     M = N = 12
     h = orc.ham(orc.REAL1D, M, N, 1.0, 6.0)
     a = orc.start_address(orc.REAL1D, M, N)
     bstart = tuple(int(x) for x in orc.column(h, a)[1][0])
     _flush("[spectral 12/12] 2 runs, N_t = 1e5, 10000 steps")
-    b = _runs(fq, 2, [7, 8], [a, bstart], a, M, N, 6.0, 1e-2, 1e5, table=400_000, spawn=2_000_000)
+    b = _runs(fq, 2, [7, 8], [a, bstart], a, M, N, 6.0, 1e-2, 1e5, table=400_000, spawn=2_000_000,
+              flags=fq.FLAG_UNCHECKED_DTAU)
     st, _ = b.run_spectral(10000)
     b.close()
     s0 = stats.shift_estimator(st[0]["shift"], skip=5000)
