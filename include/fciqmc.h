@@ -319,6 +319,23 @@ int fq_batch_replica_scratch_size(fq_batch *b, size_t *bytes);
 int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, void *scratch,
                           size_t scratch_bytes, int32_t *inexact, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as fq_batch_run_replicas, with the join's scratch taken from a
+ * static device array of FQ_STATIC_SCRATCH_BYTES inside the library
+ * instead of a caller buffer.  It makes no device allocation.  The array
+ * exists once per GPU and is held until the process ends; it is shared by
+ * every call on that GPU and keeps the last call's contents (the call
+ * clears what must start at zero), so calls that overlap in time on one GPU
+ * (other host threads, other streams) race and must not be made.  The
+ * current device must be the one that was current at fq_batch_create.
+ * Errors as fq_batch_run_replicas, and FQ_EINVAL when the scratch the batch
+ * needs (fq_batch_replica_scratch_size) exceeds FQ_STATIC_SCRATCH_BYTES:
+ * 4 MiB hold two replicas at up to 16384 buckets, eight at up to 4096. */
+#define FQ_STATIC_SCRATCH_BYTES ((size_t)4 << 20)
+int fq_batch_run_replicas_static(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps,
+                                 int32_t *inexact, void *stream);
+
 /* ------------------------------------------------------------------------
  * Excited states (Sec. 2.2): a batch of R = 2 .. FQ_MAX_REPLICAS step-
  * synchronised runs of one Hamiltonian (the same conditions as replicas),

@@ -132,6 +132,7 @@ def lib():
             "fq_batch_replica_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
             "fq_batch_run_replicas": (C.c_int, [vp, C.c_int64, vp, vp, vp, C.c_size_t,
                                                 C.POINTER(C.c_int32), vp]),
+            "fq_batch_run_replicas_static": (C.c_int, [vp, C.c_int64, vp, vp, C.POINTER(C.c_int32), vp]),
             "fq_batch_spectral_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
             "fq_batch_run_spectral": (C.c_int, [vp, C.c_int64, vp, vp, C.c_size_t, C.POINTER(C.c_int32), vp]),
             "fq_batch_destroy": (C.c_int, [vp]),
@@ -486,6 +487,25 @@ class Batch:
             msg = (lib().fq_last_error(self._inst[i].h).decode() if i >= 0
                    else lib().fq_batch_last_error(self.b).decode())
             err = FqError(rc, f"fq_batch_run_replicas: {msg}")
+            err.stats, err.overlaps, err.instance = out, ovl, i
+            raise err
+        return out, ovl, bool(inexact.value)
+
+    def run_replicas_static(self, n_steps):
+        """As run_replicas, with the join's scratch in the library's static
+        device array (fq_batch_run_replicas_static: no device allocation;
+        calls on one GPU must not overlap)."""
+        P = self.n * (self.n - 1) // 2
+        out = np.zeros((self.n, n_steps), STATS_DTYPE)
+        ovl = np.zeros((n_steps, P), np.float64)
+        inexact = C.c_int32(0)
+        rc = lib().fq_batch_run_replicas_static(self.b, n_steps, C.c_void_p(out.ctypes.data),
+                                                C.c_void_p(ovl.ctypes.data), C.byref(inexact), _stream())
+        if rc:
+            i = lib().fq_batch_failed(self.b)
+            msg = (lib().fq_last_error(self._inst[i].h).decode() if i >= 0
+                   else lib().fq_batch_last_error(self.b).decode())
+            err = FqError(rc, f"fq_batch_run_replicas_static: {msg}")
             err.stats, err.overlaps, err.instance = out, ovl, i
             raise err
         return out, ovl, bool(inexact.value)

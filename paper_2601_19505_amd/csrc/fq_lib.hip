@@ -1398,7 +1398,7 @@ hipError_t launch_overlap(const OvRun &ov, hipStream_t s)
 // null.  With ov, the replica overlaps of every step are computed and their
 // rows appended at ov->out.  Returns the status of the first failing
 // instance (grid position in *failed) after the chunk in which it failed.
-int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStream_t s, int *failed, std::string &err,
+int group_steps(Group &G, i64 steps, fq_step_stats **rows, hipStream_t s, int *failed, std::string &err,
                 OvRun *ov = nullptr, const GsRun *gs = nullptr)
 {
     const Exec &X = G.X;
@@ -1432,10 +1432,10 @@ int group_steps(Group &G, i64 steps, std::vector<fq_step_stats *> *rows, hipStre
             fq_handle *q = G.h[j];
             const Ctrl &c = G.ctrl[j];
             const i64 completed = c.step - q->step;
-            if (completed > 0 && rows && (*rows)[j]) {
-                e = hipMemcpy((*rows)[j], q->inst.ring, sizeof(StepStats) * completed, hipMemcpyDeviceToHost);
+            if (completed > 0 && rows && rows[j]) {
+                e = hipMemcpy(rows[j], q->inst.ring, sizeof(StepStats) * completed, hipMemcpyDeviceToHost);
                 if (e != hipSuccess) { err = std::string("group rows: ") + hipGetErrorString(e); return FQ_EHIP; }
-                (*rows)[j] += completed;
+                rows[j] += completed;
             }
             q->step = c.step;
             q->parity = c.parity;
@@ -1461,6 +1461,7 @@ struct fq_batch {
     std::vector<int> pos;           // caller index -> grid position
     Group G;
     int failed = -1;
+    int device = -1;                // current device at creation (owns the workspace)
     std::string err;
 };
 
@@ -1526,6 +1527,7 @@ int fq_batch_create(int32_t n, const fq_hamiltonian *h, const fq_params *p, cons
     if (bytes < total) { g_err = "batch: workspace too small"; return FQ_ENOMEM; }
     fq_batch *b = new (std::nothrow) fq_batch();
     if (!b) return FQ_ENOMEM;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = -1;
     char *ws = (char *)workspace;
     for (int i = 0; i < n; i++) {
         fq_handle *q = nullptr;
@@ -1573,7 +1575,7 @@ int fq_batch_run(fq_batch *b, int64_t n_steps, fq_step_stats *stats, void *strea
         for (int i = 0; i < n; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
     int failed = -1;
     b->failed = -1;
-    int rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err);
+    int rc = group_steps(b->G, n_steps, rows.data(), s, &failed, b->err);
     if (failed >= 0)
         for (int i = 0; i < n; i++)
             if (b->pos[i] == failed) b->failed = i;
@@ -1630,26 +1632,23 @@ int fq_batch_replica_scratch_size(fq_batch *b, size_t *bytes)
     return FQ_OK;
 }
 
-int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, void *scratch,
-                          size_t scratch_bytes, int32_t *inexact, void *stream)
+}  // extern "C"
+
+// Replica steps with overlaps (shared by fq_batch_run_replicas and the
+// allocation-free fq_batch_run_replicas_static): `sc` is device scratch of
+// at least ov_scratch(R, B).total bytes, 256-byte aligned.  Makes no device
+// allocation and no host container: R <= FQ_MAX_REPLICAS fits fixed arrays.
+static int run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, char *sc,
+                        int32_t *inexact, hipStream_t s)
 {
-    if (!b || n_steps < 0 || !overlaps) return FQ_EINVAL;
-    int rc = replica_check(b, b->err);
-    if (rc) return rc;
     const int R = (int)b->inst.size(), P = R * (R - 1) / 2;
     const fq_handle *q0 = b->inst[0];
     const OvScratch lay = ov_scratch(R, q0->R.B);
-    if (!scratch || ((uintptr_t)scratch & 255) || scratch_bytes < lay.total) {
-        b->err = "replicas: scratch must be 256-byte aligned and at least fq_batch_replica_scratch_size bytes";
-        return FQ_EINVAL;
-    }
     for (int i = 0; i < R; i++) {
         if (!b->inst[i]->have_state) { b->err = "replicas: instance " + std::to_string(i) + " has no state"; return FQ_EINVAL; }
         if (b->inst[i]->step != q0->step) { b->err = "replicas: instances are at different steps"; return FQ_EINVAL; }
     }
-    hipStream_t s = (hipStream_t)stream;
-    char *sc = (char *)scratch;
-    std::vector<const Inst *> rep(R);
+    const Inst *rep[FQ_MAX_REPLICAS];
     for (int i = 0; i < R; i++) rep[i] = b->inst[i]->d_inst;
     OvRun ov;
     ov.W = q0->R.W;
@@ -1664,20 +1663,22 @@ int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, do
     ov.O.ring_cap = RING;
     ov.O.flags = (int *)(sc + lay.flags);
     hipError_t e = ensure_lds(ov.W == 1 ? (const void *)k_overlap<1> : (const void *)k_overlap<2>, ov.lds);
-    if (e == hipSuccess) e = hipMemcpyAsync((void *)ov.O.rep, rep.data(), sizeof(Inst *) * R, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)ov.O.rep, rep, sizeof(Inst *) * R, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
+        // the flags start at zero (a fill kernel: the scratch may hold the
+        // flags of an earlier call)
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, ov.O.flags, 4, 0);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { b->err = std::string("replicas: ") + hipGetErrorString(e); return FQ_EHIP; }
     hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(256), 0, s, b->G.X.insts, R, (i64)n_steps);
-    std::vector<fq_step_stats *> rows(R, nullptr);
+    fq_step_stats *rows[FQ_MAX_REPLICAS] = {};
     if (stats)
         for (int i = 0; i < R; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
     int failed = -1;
     b->failed = -1;
-    rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err, &ov);
+    int rc = group_steps(b->G, n_steps, rows, s, &failed, b->err, &ov);
     if (failed >= 0)
         for (int i = 0; i < R; i++)
             if (b->pos[i] == failed) b->failed = i;
@@ -1690,6 +1691,73 @@ int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, do
     if (fl[0]) { b->err = "replicas: a table bucket does not fit the overlap hash (lds_slots)"; return FQ_ECAPACITY; }
     if (fl[2]) { b->err = "replicas: an amplitude product is out of the overlap range"; return FQ_EDIVERGED; }
     return FQ_OK;
+}
+
+// Device scratch of fq_batch_run_replicas_static: a file-scope array, one
+// copy per GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): it uses the address hipGetSymbolAddress returns,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[FQ_STATIC_SCRATCH_BYTES];
+constexpr int STATIC_MAX_DEVICES = 64;
+static char *g_scratch_ptr[STATIC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static int static_scratch(int dev, char **out, std::string &err)
+{
+    if (dev < 0 || dev >= STATIC_MAX_DEVICES) { err = "static scratch: device index out of range"; return FQ_EINVAL; }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("static scratch: hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return FQ_EHIP;
+        }
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FQ_OK;
+}
+
+extern "C" {
+
+int fq_batch_run_replicas(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps, void *scratch_,
+                          size_t scratch_bytes, int32_t *inexact, void *stream)
+{
+    if (!b || n_steps < 0 || !overlaps) return FQ_EINVAL;
+    int rc = replica_check(b, b->err);
+    if (rc) return rc;
+    const OvScratch lay = ov_scratch((int)b->inst.size(), b->inst[0]->R.B);
+    if (!scratch_ || ((uintptr_t)scratch_ & 255) || scratch_bytes < lay.total) {
+        b->err = "replicas: scratch must be 256-byte aligned and at least fq_batch_replica_scratch_size bytes";
+        return FQ_EINVAL;
+    }
+    return run_replicas(b, n_steps, stats, overlaps, (char *)scratch_, inexact, (hipStream_t)stream);
+}
+
+int fq_batch_run_replicas_static(fq_batch *b, int64_t n_steps, fq_step_stats *stats, double *overlaps,
+                                 int32_t *inexact, void *stream)
+{
+    if (!b || n_steps < 0 || !overlaps) return FQ_EINVAL;
+    int rc = replica_check(b, b->err);
+    if (rc) return rc;
+    const OvScratch lay = ov_scratch((int)b->inst.size(), b->inst[0]->R.B);
+    if (lay.total > FQ_STATIC_SCRATCH_BYTES) {
+        b->err = "replicas (static scratch): " + std::to_string(lay.total) + " bytes of scratch needed, the static "
+                 "scratch holds " + std::to_string((size_t)FQ_STATIC_SCRATCH_BYTES) +
+                 " (fewer replicas or buckets, or fq_batch_run_replicas with a caller buffer)";
+        return FQ_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device) {
+        b->err = "replicas (static scratch): the current device is not the batch's device";
+        return FQ_EINVAL;
+    }
+    char *sc = nullptr;
+    rc = static_scratch(dev, &sc, b->err);
+    if (rc) return rc;
+    return run_replicas(b, n_steps, stats, overlaps, sc, inexact, (hipStream_t)stream);
 }
 
 struct GsScratch {
@@ -1783,7 +1851,7 @@ int fq_batch_run_spectral(fq_batch *b, int64_t n_steps, fq_step_stats *stats, vo
         for (int i = 0; i < R; i++) rows[b->pos[i]] = stats + (size_t)i * n_steps;
     int failed = -1;
     b->failed = -1;
-    rc = group_steps(b->G, n_steps, &rows, s, &failed, b->err, nullptr, &g);
+    rc = group_steps(b->G, n_steps, rows.data(), s, &failed, b->err, nullptr, &g);
     if (failed >= 0)
         for (int i = 0; i < R; i++)
             if (b->pos[i] == failed) b->failed = i;
@@ -2010,7 +2078,7 @@ int fq_server_tick(fq_server *sv, void *stream, int32_t *n_active, int32_t *n_qu
         for (int j = 0; j < n; j++) rows[j] = sv->rowbuf.data() + (size_t)j * T;
         int failed = -1;
         std::string err;
-        int rc = group_steps(sv->G, T, &rows, s, &failed, err);
+        int rc = group_steps(sv->G, T, rows.data(), s, &failed, err);
         if (rc == FQ_EHIP) { sv->err = err; return rc; }
         // account the rows and retire finished or failed solves
         std::unordered_map<const fq_handle *, int> posof;
