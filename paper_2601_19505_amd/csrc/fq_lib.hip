@@ -23,6 +23,7 @@
 #include <unordered_map>
 
 #include "fciqmc.h"
+#include "fq_kernels.hpp"
 #include "fq_overlap.hpp"
 #include "fq_step.hpp"
 
@@ -30,41 +31,10 @@ using namespace fq;
 
 // ------------------------------------------------------------------ kernels
 //
-// The step kernels run over a set of instances: one, or a batch.  `insts` is
-// a device array of instance descriptors.  A merge or spawn workgroup finds
-// its instance and bucket through `map` (entry = instance << 14 | bucket);
-// without a map there is one instance and workgroup b takes bucket b.
+// The merge and spawn kernels (fq_kernels.hpp) are instantiated in
+// fq_inst.hip, one translation unit per (W, model variant).
 
-__device__ __forceinline__ const Inst &locate(const Inst *const *insts, const u32 *map, int &b)
-{
-    if (map) {
-        const u32 m = map[blockIdx.x];
-        b = (int)(m & 0x3fffu);
-        return const_inst(insts[m >> 14]);
-    }
-    b = (int)blockIdx.x;
-    return const_inst(insts[0]);
-}
-
-// EARLY: early compression (separate kernels, so the late-compression
-// kernels carry none of its code and registers)
-template <int W, int MODEL, int BS, bool EARLY>
-__global__ __launch_bounds__(BS) void k_merge(const Inst *const *insts, const u32 *map)
-{
-    extern __shared__ __align__(16) char smem[];
-    int b;
-    const Inst &I = locate(insts, map, b);
-    merge_bucket<W, MODEL, BS, EARLY>(I, b, smem);
-}
-
-template <int W, int MODEL, int BS, bool EARLY>
-__global__ __launch_bounds__(BS) void k_spawn(const Inst *const *insts, const u32 *map, int mode)
-{
-    extern __shared__ __align__(16) char smem[];
-    int b;
-    const Inst &I = locate(insts, map, b);
-    spawn_bucket<W, MODEL, BS, EARLY>(I, b, mode, smem);
-}
+FQ_EXTERN_STEP_KERNELS
 
 // one workgroup per instance
 #ifndef FQ_FIN_BS
