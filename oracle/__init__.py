@@ -44,7 +44,8 @@ class Ham(C.Structure):
 class Params(C.Structure):
     _fields_ = [("h", Ham), ("dtau", C.c_double), ("target", C.c_double), ("zeta", C.c_double),
                 ("xi", C.c_double), ("theta", C.c_double), ("t_rel", C.c_double),
-                ("seed", C.c_uint64), ("early", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("early", C.c_int32), ("initiator", C.c_int32),
+                ("n_a", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -267,11 +268,14 @@ def validate(h):
 # --------------------------------------------------------------------------
 
 def params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target=1000.0, zeta=0.08, xi=None,
-           theta=1.0, t_rel=1.0, seed=0, early=False, lx=0, g=0.0):
+           theta=1.0, t_rel=1.0, seed=0, early=False, lx=0, g=0.0, initiator=None):
+    """FCIQMC parameters; `initiator` is the threshold n_a of the initiator
+    rule (None: the rule is off)."""
     if xi is None:
         xi = zeta * zeta / 4.0
     return Params(ham(model, M, N, t, u, lx, g), dtau, target, zeta, xi, theta, t_rel, seed,
-                  1 if early else 0, 0)
+                  1 if early else 0, 0 if initiator is None else 1,
+                  0.0 if initiator is None else float(initiator))
 
 
 def _addr2(addrs):

@@ -40,7 +40,8 @@ typedef struct {
     double dtau, target, zeta, xi, theta, t_rel;
     uint64_t seed;
     int32_t early;   /* 0: late compression (default); 1: early compression (Sec. 7.1) */
-    int32_t reserved;
+    int32_t initiator; /* 1: initiator rule with threshold n_a (Sec. 1, sign-problem paragraph of Sec. 3.2) */
+    double n_a;
 } orc_params;
 
 typedef struct {
@@ -591,9 +592,12 @@ static int column_pick(const orc_ham *H, const orc_col *c, const int32_t *occ, u
 /* projected energy Eq. ProjectedEnergy of Sec. 4.2).                        */
 /* ------------------------------------------------------------------------ */
 
+/* kind: 0 diagonal survivor, 1 spawn from an initiator (or any spawn when
+ * the initiator rule is off), 2 spawn from a non-initiator */
 typedef struct {
     uint64_t a[2];
     double v;
+    int32_t kind;
 } orc_rec;
 
 static int rec_cmp(const void *x, const void *y)
@@ -712,6 +716,19 @@ static double early_u(uint64_t seed, const uint64_t *a, int64_t step, int diag, 
  * with the tag-2 draw of its address and to spawn attempt k with the draw
  * of early_u; contributions compressed to 0 are dropped (they are not
  * spawn events), and the sums are kept as they are.
+ *
+ * With P->initiator set (the initiator approximation of Cleland, Booth and
+ * Alavi, which the paper names in Sec. 1 and in the sign-problem paragraph
+ * of Sec. 3.2 without stating it; reading): entry i is an initiator when
+ * |c_i| > n_a.  Steps 1 and 2 are unchanged, and every spawn event is still
+ * generated, dumped and counted in `spawns`.  In step 3 a spawn of a
+ * non-initiator parent counts only when its destination is occupied in
+ * c^(n), i.e. is an address of the input table; otherwise it is discarded.
+ * Survivors and spawns of initiators always count.  Every input address
+ * takes part in the merge (its survivor is recorded even when it is 0), so
+ * the merged dump lists the input addresses and the destinations that
+ * received a counted spawn.  n_a = 0 makes every nonzero entry an initiator
+ * and gives the plain step.
  */
 int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64_t n,
              double shift, int64_t step, const uint64_t *ref, double yref,
@@ -721,6 +738,7 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
 {
     const orc_ham *H = &P->h;
     if (orc_validate(H)) return ORC_EINVAL;
+    if (P->initiator && !(P->n_a >= 0.0)) return ORC_EINVAL;
     int M = H->M, N = H->N;
     int rc = ORC_OK;
     /* pass 1: count records */
@@ -760,7 +778,10 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
         double g = 1.0 + P->dtau * (shift - hii);
         double sv = ci * g;
         if (P->early) sv = compress1(sv, P->theta, early_u(P->seed, a, step, 1, 0));
-        if (sv != 0.0) { rec[nr].a[0] = a[0]; rec[nr].a[1] = a[1]; rec[nr].v = sv; nr++; }
+        if (sv != 0.0 || P->initiator) {
+            rec[nr].a[0] = a[0]; rec[nr].a[1] = a[1]; rec[nr].v = sv; rec[nr].kind = 0; nr++;
+        }
+        const int32_t skind = (P->initiator && !(fabs(ci) > P->n_a)) ? 2 : 1;
         orc_col c;
         rc = ham_column(H, occ, &c);
         if (rc) { col_free(&c); free(rec); return rc; }
@@ -771,7 +792,8 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
                 double v = (-(P->dtau * c.h[k])) * ci;
                 if (P->early) v = compress1(v, P->theta, early_u(P->seed, a, step, 0, k));
                 if (v == 0.0) continue;
-                rec[nr].a[0] = c.dest[k][0]; rec[nr].a[1] = c.dest[k][1]; rec[nr].v = v; nr++;
+                rec[nr].a[0] = c.dest[k][0]; rec[nr].a[1] = c.dest[k][1]; rec[nr].v = v;
+                rec[nr].kind = skind; nr++;
                 if (ev && nev < ev_cap) {
                     ev[nev].parent = i; ev[nev].attempt = k;
                     ev[nev].dest[0] = c.dest[k][0]; ev[nev].dest[1] = c.dest[k][1];
@@ -800,7 +822,8 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
                 double v = ((-(P->dtau * c.h[e])) * ci) * q;
                 if (P->early) v = compress1(v, P->theta, early_u(P->seed, a, step, 0, k));
                 if (v == 0.0) continue;
-                rec[nr].a[0] = c.dest[e][0]; rec[nr].a[1] = c.dest[e][1]; rec[nr].v = v; nr++;
+                rec[nr].a[0] = c.dest[e][0]; rec[nr].a[1] = c.dest[e][1]; rec[nr].v = v;
+                rec[nr].kind = skind; nr++;
                 if (ev && nev < ev_cap) {
                     ev[nev].parent = i; ev[nev].attempt = k;
                     ev[nev].dest[0] = c.dest[e][0]; ev[nev].dest[1] = c.dest[e][1];
@@ -821,11 +844,17 @@ int orc_step(const orc_params *P, const uint64_t *addr, const double *val, int64
     int64_t nout = 0, nmg = 0;
     for (int64_t s = 0; s < nr;) {
         int64_t e = s;
+        int occupied = 0, counted = 0;
         while (e < nr && rec[e].a[0] == rec[s].a[0] && rec[e].a[1] == rec[s].a[1]) {
-            buf[e - s] = rec[e].v;
+            if (rec[e].kind == 0) occupied = 1;
             e++;
         }
-        double w = orc_fsum(buf, e - s);
+        /* the group's counted contributions (all of them without the
+         * initiator rule) */
+        for (int64_t k = s; k < e; k++)
+            if (rec[k].kind != 2 || occupied) buf[counted++] = rec[k].v;
+        if (counted == 0) { s = e; continue; }
+        double w = orc_fsum(buf, counted);
         if (mg_addr && nmg < mg_cap) {
             mg_addr[2 * nmg] = rec[s].a[0]; mg_addr[2 * nmg + 1] = rec[s].a[1]; mg_val[nmg] = w;
         }
