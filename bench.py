@@ -239,11 +239,20 @@ def _spec(inst, **lay):
 BATCH_LAYOUT = dict(lds_slots=2048, block=512, spawn_block=256)
 
 
-def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
+# shared layouts the batch autotuner tries (hash and tile shapes)
+BATCH_CANDIDATES = [dict(lds_slots=sl, block=bl, spawn_block=sb)
+                    for sl in (1024, 2048, 4096) for bl in (256, 512, 1024) for sb in (256, 512)
+                    if sl <= 8 * bl]
+
+
+def bench_batched(fq, torch, n=64, warmup=1500, steps=500, trial_steps=20):
     """The 64-instance batch (real-space, M = N in 8..24, u log-uniform in
-    [1, 10], N_t 1e4..1e7): walker-steps/s of the batch against the same
-    instances stepped one at a time (plain per-instance launches), from the
-    same state; the two runs must agree bit for bit."""
+    [1, 10], N_t 1e4..1e7) after `warmup` steps: walker-steps/s of the batch
+    with the fixed layout, of the batch with the layout the batch autotuner
+    picks (fq_batch_autotune over BATCH_CANDIDATES, timed on device copies
+    of the states), and of the same instances stepped one at a time (plain
+    per-instance launches), all from the same state; the three runs must
+    agree bit for bit."""
     specs = [_spec(x, **BATCH_LAYOUT) for x in synthetic.batch_instances(n)]
     b = fq.Batch(specs)
     for i, sp in enumerate(specs):
@@ -256,6 +265,13 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
         b.run(k)
         done += k
         log(f"[bench] batch warmup {done}/{warmup} ({time.perf_counter() - t0:.1f} s)")
+    ms, best = b.autotune(BATCH_CANDIDATES, trial_steps=trial_steps)
+    tuned_layout = BATCH_CANDIDATES[best]
+    log(f"[bench] batch autotune: best {tuned_layout} {ms[best]:.3f} ms/step over {len(ms)} candidates")
+    tspecs = [dict(sp, buckets=0, **tuned_layout) for sp in specs]
+    tb = fq.Batch(tspecs)
+    for i in range(n):
+        tb.instance(i).copy_state_from(b.instance(i))
     plain = []
     for i, sp in enumerate(specs):
         s = fq.Solver(**sp)
@@ -266,6 +282,12 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
     st = b.run(steps)
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    stt = tb.run(steps)
+    torch.cuda.synchronize()
+    wall_t = time.perf_counter() - t1
+    same_t = stt.tobytes() == st.tobytes()
+    tb.close()
     wall_p = 0.0
     same = True
     for i, s in enumerate(plain):
@@ -281,11 +303,16 @@ def bench_batched(fq, torch, n=64, warmup=1500, steps=500):
     out = dict(workload=f"batch of {n} real-space 1D Bose-Hubbard instances (M = N in 8..24, "
                         f"u log-uniform in [1, 10], N_t 1e4..1e7)",
                instances=n, warmup=warmup, steps=steps, walkers_total=float(st["norm"][:, -1].sum()),
-               walker_steps_per_s=ws / wall_b, ms_per_step=wall_b / steps * 1e3,
+               layout=dict(BATCH_LAYOUT), walker_steps_per_s=ws / wall_b, ms_per_step=wall_b / steps * 1e3,
+               autotuned=dict(layout=tuned_layout, candidates=len(ms), trial_steps=trial_steps,
+                              trial_ms_per_step=float(ms[best]),
+                              walker_steps_per_s=ws / wall_t, ms_per_step=wall_t / steps * 1e3,
+                              identical_to_fixed=bool(same_t)),
                plain_walker_steps_per_s=ws / wall_p, plain_ms_per_step=wall_p / steps * 1e3,
-               speedup_vs_plain=wall_p / wall_b, identical_to_plain=bool(same))
-    log(f"[bench] batched {out['walker_steps_per_s']:.4g} walker-steps/s, plain "
-        f"{out['plain_walker_steps_per_s']:.4g} ({out['speedup_vs_plain']:.2f}x), identical {same}")
+               speedup_vs_plain=wall_p / min(wall_b, wall_t), identical_to_plain=bool(same))
+    log(f"[bench] batched {out['walker_steps_per_s']:.4g} walker-steps/s (fixed), "
+        f"{out['autotuned']['walker_steps_per_s']:.4g} (autotuned {tuned_layout}), plain "
+        f"{out['plain_walker_steps_per_s']:.4g}, identical {same} {same_t}")
     return out
 
 
@@ -370,24 +397,19 @@ def bench_replicas(fq, torch, wl, cfg, warmup=100, steps=300, settle=500):
     return out
 
 
-def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
-    """The first n_req requests of the Poisson stream (lambda = 50/s, M = N in
-    6..20, u in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7]) served
-    with continuous batching under an HBM budget; latency = completion -
-    arrival."""
-    reqs = synthetic.poisson_requests(1000)[:n_req]
-    free = torch.cuda.mem_get_info()[0]
-    pool = int(min(budget, 0.85 * free))
+def _serve(fq, torch, reqs, pool, tick, max_active, t_arrival, log_every=20):
+    """Serve `reqs` (arrival offsets t_arrival, seconds) with continuous
+    batching.  Returns per-request (arrival, admission, completion) times,
+    walker-steps and the number of ticks."""
     sv = fq.Server(fq.REAL1D, pool, lds_slots=BATCH_LAYOUT["lds_slots"], block=BATCH_LAYOUT["block"],
-                   spawn_block=BATCH_LAYOUT["spawn_block"], max_active=max_active,
-                   steps_per_tick=tick)
-    ids, comp = [], {}
+                   spawn_block=BATCH_LAYOUT["spawn_block"], max_active=max_active, steps_per_tick=tick)
+    n = len(reqs)
+    ids, adm, comp = [], {}, {}
     t0 = time.perf_counter()
-    i = 0
-    ticks = 0
-    while len(comp) < n_req:
+    i, ticks, max_queued = 0, 0, 0
+    while len(comp) < n:
         now = time.perf_counter() - t0
-        while i < n_req and reqs[i]["arrival"] - reqs[0]["arrival"] <= now:
+        while i < n and t_arrival[i] <= now:
             r = reqs[i]
             sp = _spec(r)
             sp.pop("addr_words")
@@ -395,36 +417,111 @@ def bench_served(fq, torch, n_req=24, tick=250, budget=200e9, max_active=128):
             i += 1
         active, queued, fin = sv.tick()
         ticks += 1
+        max_queued = max(max_queued, queued)
         now = time.perf_counter() - t0
         for k, rid in enumerate(ids):
-            if rid not in comp and sv.poll(rid)["state"] >= fq.REQ_DONE:
+            if rid in comp:
+                continue
+            st = sv.poll(rid)["state"]
+            if st >= fq.REQ_RUNNING and rid not in adm:
+                adm[rid] = now
+            if st >= fq.REQ_DONE:
                 comp[rid] = now
-        if active == 0 and queued == 0 and i < n_req:
-            time.sleep(max(0.0, reqs[i]["arrival"] - reqs[0]["arrival"] - now))
-        if ticks % 20 == 0:
-            log(f"[bench] served: {len(comp)}/{n_req} done, {active} active, {queued} queued "
-                f"({now:.1f} s)")
-    lat, ws, ok = [], 0.0, True
-    for k, rid in enumerate(ids):
+        if active == 0 and queued == 0 and i < n:
+            time.sleep(max(0.0, t_arrival[i] - now))
+        if ticks % log_every == 0:
+            log(f"[bench] served: {len(comp)}/{n} done, {active} active, {queued} queued, "
+                f"{i} arrived ({now:.1f} s)")
+    ws, ok = [], True
+    for rid in ids:
         info = sv.poll(rid)
         ok &= info["state"] == fq.REQ_DONE
-        lat.append(comp[rid] - (reqs[k]["arrival"] - reqs[0]["arrival"]))
-        ws += info["walker_steps"]
-    makespan = max(comp.values())
+        ws.append(info["walker_steps"])
     sv.close()
-    out = dict(workload=f"first {n_req} requests of a Poisson stream (lambda = 50/s; real-space "
-                        "M = N in 6..20, u in [1, 10], 2e3..2e4 steps, N_t log-uniform in "
-                        "[1e3, 1e7]), continuous batching",
-               requests=n_req, pool_bytes=pool, steps_per_tick=tick, ticks=ticks,
-               p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
-               walker_steps_per_s=ws / makespan, makespan_s=makespan, all_done=bool(ok),
-               mean_walker_steps_per_request=ws / n_req,
-               # largest arrival rate whose work the GPU keeps up with (beyond
-               # it the queue, and the p99 latency, grow without bound)
-               capacity_requests_per_s=(ws / makespan) / (ws / n_req))
+    arr = np.asarray(t_arrival[:n])
+    return dict(arrival=arr, admit=np.array([adm[r] for r in ids]), done=np.array([comp[r] for r in ids]),
+                walker_steps=np.asarray(ws), ticks=ticks, max_queued=max_queued, all_done=bool(ok))
+
+
+def bench_served(fq, torch, n_req=100, tick=250, budget=200e9, max_active=128, load=0.8, n_calib=16,
+                 plain=True):
+    """The Poisson request stream of real-space solves (M = N in 6..20, u in
+    [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7]) served with
+    continuous batching under an HBM budget.
+
+    1. Capacity: a burst of the first n_calib requests gives the served
+       throughput; capacity = requests per second the GPU completes for this
+       request mix.
+    2. Stream: the first n_req requests of the stream, their arrival times
+       rescaled to the rate load x capacity (the configured 50/s is far above
+       what one GPU completes for requests of about 5e9 walker-steps each).
+       Latency = completion - arrival, queue wait = admission - arrival.
+    3. Plain: the same requests served one at a time in arrival order by a
+       plain solver each (no batching): every request's service time is
+       measured alone, and the latencies follow from the same arrival times
+       (first come, first served on one GPU)."""
+    reqs = synthetic.poisson_requests(1000)
+    free = torch.cuda.mem_get_info()[0]
+    pool = int(min(budget, 0.85 * free))
+    # 1. capacity from a burst
+    cal = _serve(fq, torch, reqs[:n_calib], pool, tick, max_active, [0.0] * n_calib, log_every=50)
+    cal_make = float(cal["done"].max())
+    capacity = n_calib / cal_make
+    rate = load * capacity
+    log(f"[bench] served capacity {capacity:.2f} requests/s (burst of {n_calib}); stream at {rate:.2f}/s")
+    # 2. the stream at rate
+    base = np.array([r["arrival"] for r in reqs[:n_req]])
+    t_arr = (base - base[0]) * (50.0 / rate)
+    sv = _serve(fq, torch, reqs[:n_req], pool, tick, max_active, list(t_arr))
+    lat = sv["done"] - sv["arrival"]
+    wait = sv["admit"] - sv["arrival"]
+    makespan = float(sv["done"].max())
+    ws = float(sv["walker_steps"].sum())
+    out = dict(workload=f"first {n_req} requests of a Poisson stream of real-space solves (M = N in 6..20, "
+                        "u in [1, 10], 2e3..2e4 steps, N_t log-uniform in [1e3, 1e7]), continuous batching, "
+                        f"arrivals rescaled to {load} x the measured capacity",
+               requests=n_req, pool_bytes=pool, steps_per_tick=tick, max_active=max_active,
+               capacity_requests_per_s=capacity, capacity_burst_requests=n_calib, load=load,
+               arrival_rate_per_s=rate, ticks=sv["ticks"], max_queued=sv["max_queued"],
+               p50_latency_s=float(np.percentile(lat, 50)), p90_latency_s=float(np.percentile(lat, 90)),
+               p99_latency_s=float(np.percentile(lat, 99)), mean_queue_wait_s=float(wait.mean()),
+               p99_queue_wait_s=float(np.percentile(wait, 99)),
+               queued_requests=int(np.sum(wait > 1e-3)),
+               walker_steps_per_s=ws / makespan, makespan_s=makespan, all_done=sv["all_done"],
+               mean_walker_steps_per_request=ws / n_req)
     log(f"[bench] served p50 {out['p50_latency_s']:.2f} s p99 {out['p99_latency_s']:.2f} s, "
-        f"{out['walker_steps_per_s']:.4g} walker-steps/s, capacity {out['capacity_requests_per_s']:.2f} "
-        f"requests/s")
+        f"{out['walker_steps_per_s']:.4g} walker-steps/s, {out['queued_requests']} requests queued "
+        f"(max {out['max_queued']} at once)")
+    if plain:
+        # 3. one at a time: measured service times, FIFO on the same arrivals
+        svc = np.zeros(n_req)
+        t0 = time.perf_counter()
+        for k, r in enumerate(reqs[:n_req]):
+            sp = _spec(r, **BATCH_LAYOUT)
+            s = fq.Solver(**sp)
+            a = fq.start_address(r["model"], r["M"], r["N"])
+            s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s.run(r["steps"])
+            torch.cuda.synchronize()
+            svc[k] = time.perf_counter() - t1
+            s.close()
+            if k % 10 == 9:
+                log(f"[bench] plain service {k + 1}/{n_req} ({time.perf_counter() - t0:.1f} s)")
+        fin = np.zeros(n_req)
+        for k in range(n_req):
+            fin[k] = max(t_arr[k], fin[k - 1] if k else 0.0) + svc[k]
+        plat = fin - t_arr
+        out["plain"] = dict(rule="each request alone on a plain solver, first come first served on the "
+                                 "same arrival times; service times measured",
+                            p50_latency_s=float(np.percentile(plat, 50)),
+                            p99_latency_s=float(np.percentile(plat, 99)),
+                            walker_steps_per_s=ws / float(svc.sum()), makespan_s=float(fin.max()),
+                            service_s_total=float(svc.sum()))
+        out["speedup_vs_plain"] = out["walker_steps_per_s"] / out["plain"]["walker_steps_per_s"]
+        log(f"[bench] plain p50 {out['plain']['p50_latency_s']:.2f} s p99 {out['plain']['p99_latency_s']:.2f} s, "
+            f"{out['plain']['walker_steps_per_s']:.4g} walker-steps/s")
     return out
 
 
@@ -527,7 +624,9 @@ def main():
                     help="skip the 6 x 6 lattice measurement (the paper's benchmark system)")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--batch-warmup", type=int, default=1500)
-    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--no-serve-plain", action="store_true",
+                    help="skip the one-at-a-time comparison of the served stream")
     ap.add_argument("--compression-study", action="store_true",
                     help="only compare late and early compression by statistical efficiency")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -691,7 +790,7 @@ def main():
         out["batched"] = bench_batched(fq, torch, warmup=args.batch_warmup, steps=args.batch_steps)
         torch.cuda.empty_cache()
     if not args.no_serve:
-        out["served"] = bench_served(fq, torch, n_req=args.serve_requests)
+        out["served"] = bench_served(fq, torch, n_req=args.serve_requests, plain=not args.no_serve_plain)
         torch.cuda.empty_cache()
     if state is not None:
         addrs, vals, shift, step = state

@@ -254,8 +254,9 @@ int fq_autotune(fq_handle *src, const fq_layout *candidates, int32_t n, int32_t 
  * from a map), with per-instance tables, shifts and statistics.  Instances
  * may differ in Hamiltonian (M, N, t, u, g), parameters and capacities;
  * they must share the model kind (the ring without importance sampling; the
- * square lattice or a ring with g != 0; momentum space with M <= 16 or
- * M <= 32), the compression style (FQ_FLAG_EARLY_COMPRESSION set or not),
+ * square lattice or a ring with g != 0; momentum space with one-word
+ * addresses of at most 31 bits, N + M - 1 <= 31, or other momentum space),
+ * the compression style (FQ_FLAG_EARLY_COMPRESSION set or not),
  * addr_words, lds_slots, block and spawn_block.  Every instance
  * produces the same results as it would alone.
  *
@@ -283,6 +284,21 @@ int fq_batch_destroy(fq_batch *b);
  * failed fq_batch_create); instance failures are also reported by
  * fq_last_error() of the instance that fq_batch_failed() names. */
 const char *fq_batch_last_error(const fq_batch *b);
+/* fq_batch_autotune times candidate shared layouts of a batch (the hash and
+ * tile shapes every instance shares: lds_slots, block and spawn_block; the
+ * bucket count of every instance is the candidate's `buckets`, or follows
+ * from the instance's capacities and the candidate's lds_slots when 0):
+ * for each of the n candidates it creates a batch of the same instances
+ * with that layout in `scratch` (caller-owned device memory of at least
+ * that batch's fq_batch_workspace_size), copies every instance's state into
+ * it on the device, runs one step, then times trial_steps steps of the
+ * whole batch with HIP events on `stream`.  ms[i] = milliseconds per step
+ * of candidate i, negative when it does not fit `scratch` or fails; *best =
+ * the index of the fastest.  The results of a batch do not depend on its
+ * layout, so a batch re-created with the best layout (and the states copied
+ * over) continues exactly.  `b` is not modified. */
+int fq_batch_autotune(fq_batch *b, const fq_layout *candidates, int32_t n, int32_t trial_steps, void *scratch,
+                      size_t scratch_bytes, double *ms, int32_t *best, void *stream);
 
 /* ------------------------------------------------------------------------
  * Replicas (Sec. 4.3, Eq. RayleighQuotientReplica): a batch of R = 2 ..
@@ -383,7 +399,8 @@ int fq_batch_run_spectral(fq_batch *b, int64_t n_steps, fq_step_stats *stats, vo
  * fq_server_poll reports a request's state, its last statistics row and the
  * means of shift, y.Hc and y.c over the steps after the first half.  All
  * requests of one server share the model, addr_words, lds_slots, block and
- * spawn_block of its configuration (momentum space: M <= 16) and use late
+ * spawn_block of its configuration (momentum space: addr_words 1 and
+ * N + M - 1 <= 31) and use late
  * compression (a request with FQ_FLAG_EARLY_COMPRESSION is refused with
  * FQ_EINVAL); a ring server takes g = 0 only.  Not thread safe.
  * ------------------------------------------------------------------------ */

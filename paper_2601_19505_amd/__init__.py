@@ -128,6 +128,8 @@ def lib():
             "fq_batch_instance": (C.c_int, [vp, C.c_int32, P(vp)]),
             "fq_batch_run": (C.c_int, [vp, C.c_int64, vp, vp]),
             "fq_batch_failed": (C.c_int32, [vp]),
+            "fq_batch_autotune": (C.c_int, [vp, P(Layout), C.c_int32, C.c_int32, vp, C.c_size_t, f64p,
+                                            i32p, vp]),
             "fq_batch_last_error": (C.c_char_p, [vp]),
             "fq_batch_replica_scratch_size": (C.c_int, [vp, C.POINTER(C.c_size_t)]),
             "fq_batch_run_replicas": (C.c_int, [vp, C.c_int64, vp, vp, vp, C.c_size_t,
@@ -461,6 +463,36 @@ class Batch:
             err.instance = i
             raise err
         return out
+
+    def autotune(self, candidates, trial_steps=20):
+        """Time candidate shared layouts (dicts of buckets, lds_slots, block,
+        spawn_block) for the whole batch on device copies of its states
+        (fq_batch_autotune).  Returns (ms per step for each candidate, or -1,
+        index of the fastest).  The batch is not changed."""
+        import torch
+        lays = (Layout * len(candidates))()
+        need = 0
+        for i, c in enumerate(candidates):
+            lays[i] = _layout(0, 0, c.get("buckets", 0), c.get("lds_slots", 0), c.get("block", 0),
+                              c.get("spawn_block", 0))
+            ls = (Layout * self.n)()
+            for j in range(self.n):
+                lo = self._inst[j].get_layout()
+                ls[j] = _layout(lo.table_capacity, lo.spawn_capacity, c.get("buckets", 0),
+                                c.get("lds_slots", 0), c.get("block", 0), c.get("spawn_block", 0))
+            nb = C.c_size_t(0)
+            if lib().fq_batch_workspace_size(self.n, self.hams, self.params, ls, C.byref(nb)) == 0:
+                need = max(need, nb.value)
+        scratch = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        ms = np.zeros(len(candidates))
+        best = C.c_int32(-1)
+        rc = lib().fq_batch_autotune(self.b, lays, len(candidates), int(trial_steps),
+                                     C.c_void_p(scratch.data_ptr()), scratch.numel(), _p(ms, C.c_double),
+                                     C.byref(best), _stream())
+        del scratch
+        if rc:
+            raise FqError(rc, f"fq_batch_autotune: {lib().fq_batch_last_error(self.b).decode()}")
+        return ms, best.value
 
     def run_replicas(self, n_steps):
         """Advance every instance as replicas of one Hamiltonian (Sec. 4.3)

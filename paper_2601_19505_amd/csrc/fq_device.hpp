@@ -198,12 +198,40 @@ __device__ __forceinline__ u64 addr_hash(u64 a) { return mix64(a); }
 __device__ __forceinline__ u64 addr_hash(U128 a) { return mix64(a.lo ^ mix64(a.hi + 0x9e3779b97f4a7c15ull)); }
 // bucket = top log2B bits, LDS slot = low bits
 __device__ __forceinline__ u32 bucket_of(u64 h, int log2B) { return log2B == 0 ? 0u : (u32)(h >> (64 - log2B)); }
+// 32-bit finalizer (the lowbias32 constants) for addresses of at most 32 bits
+__device__ __forceinline__ u32 hash32(u32 x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+// The hash bucket of an address (log2B <= 14): the top log2B bits of a hash
+// of the address.  Addresses that fit 32 bits (one word, N + M - 1 <= 32:
+// `narrow`, the same for every address of an instance) use the 32-bit
+// finalizer, others the 64-bit one.  Any well-mixed function serves: the
+// bucket only places an address, and results do not depend on it.
+__device__ __forceinline__ u32 bucket_index(u64 a, int log2B, bool narrow)
+{
+    if (log2B == 0) return 0u;
+    return narrow ? hash32((u32)a) >> (32 - log2B) : (u32)(mix64(a) >> (64 - log2B));
+}
+__device__ __forceinline__ u32 bucket_index(U128 a, int log2B, bool)
+{
+    return bucket_of(addr_hash(a), log2B);
+}
 
 // ---------------------------------------------------------------- Philox
 
 struct R4 {
     u32 x, y, z, w;
 };
+
+// a ^ b ^ c in one instruction (gfx950 three-input bit operation, truth
+// table 0x96)
+__device__ __forceinline__ u32 xor3(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
 
 // Philox4x32-10: ten rounds of the 4x32 S-box with the Weyl key schedule.
 __device__ __forceinline__ R4 philox4x32_10(u32 c0, u32 c1, u32 c2, u32 c3, u32 k0, u32 k1)
@@ -212,7 +240,7 @@ __device__ __forceinline__ R4 philox4x32_10(u32 c0, u32 c1, u32 c2, u32 c3, u32 
     for (int r = 0; r < 10; r++) {
         // one 32x32 -> 64 product gives both halves (v_mad_u64_u32)
         const u64 p0 = (u64)0xD2511F53u * c0, p1 = (u64)0xCD9E8D57u * c2;
-        const u32 y0 = (u32)(p1 >> 32) ^ c1 ^ k0, y2 = (u32)(p0 >> 32) ^ c3 ^ k1;
+        const u32 y0 = xor3((u32)(p1 >> 32), c1, k0), y2 = xor3((u32)(p0 >> 32), c3, k1);
         c0 = y0; c1 = (u32)p1; c2 = y2; c3 = (u32)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

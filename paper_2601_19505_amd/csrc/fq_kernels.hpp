@@ -35,8 +35,13 @@ __global__ __launch_bounds__(BS) void k_merge(const fq::Inst *const *insts, cons
     fq::merge_bucket<W, MODEL, BS, EARLY>(I, b, smem);
 }
 
+// waves per SIMD the spawn kernel's register budget must allow (1: no
+// constraint beyond the workgroup size)
+#ifndef FQ_SPAWN_WAVES
+#define FQ_SPAWN_WAVES 1
+#endif
 template <int W, int MODEL, int BS, bool EARLY>
-__global__ __launch_bounds__(BS) void k_spawn(const fq::Inst *const *insts, const fq::u32 *map, int mode)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(FQ_SPAWN_WAVES))) void k_spawn(const fq::Inst *const *insts, const fq::u32 *map, int mode)
 {
     extern __shared__ __align__(16) char smem[];
     int b;

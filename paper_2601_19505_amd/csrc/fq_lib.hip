@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_insert(const Inst *Ip, const u64 *sa, c
     for (i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
         u64 a0 = sa[i * W], a1 = W == 2 ? sa[i * W + 1] : 0;
         double v = sv[i];
-        u32 b = bucket_of(addr_hash(AddrOf<W>::make(a0, a1)), I.log2B);
+        u32 b = bucket_index(AddrOf<W>::make(a0, a1), I.log2B, I.mc.nb <= 32);
         int pos = atomicAdd(&I.tab_n[p][b], 1);
         if (pos >= I.cap_t) { set_error(ctrl, FQE_CAP_TABLE, (int)b); continue; }
         i64 o = (i64)b * I.cap_t + pos;
@@ -194,7 +194,7 @@ __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *
     oa[0] = r0;
     oa[1] = r1;
     oh[0] = hd;
-    ob[0] = (int)bucket_of(addr_hash(a), I.log2B);
+    ob[0] = (int)bucket_index(a, I.log2B, I.mc.nb <= 32);
     for (i64 e = 0; e < m; e++) {
         double h;
         T d;
@@ -211,7 +211,7 @@ __global__ void k_ref(const Inst *Ip, u64 r0, u64 r1, u64 *oa, double *oh, int *
         oa[2 * (e + 1)] = word0(d);
         oa[2 * (e + 1) + 1] = word1(d);
         oh[e + 1] = h;
-        ob[e + 1] = (int)bucket_of(addr_hash(d), I.log2B);
+        ob[e + 1] = (int)bucket_index(d, I.log2B, I.mc.nb <= 32);
     }
     *on = (int)m + 1;
 }
@@ -262,12 +262,14 @@ const void *pick_kernel(int bs, bool spawn, bool early)
     return early ? pick_bs<W, MODEL, true>(bs, spawn) : pick_bs<W, MODEL, false>(bs, spawn);
 }
 
-// kernel variant: 0 real-space ring, 1 momentum space with M <= 16, 2
-// momentum with M <= 32, 3 lattice (the square lattice, or the ring with
-// importance sampling); plus 4 with early compression
-int variant(int model, int M, double g, int flags)
+// kernel variant: 0 real-space ring, 1 momentum space with addresses of one
+// word and at most 31 bits (N + M - 1 <= 31), 2 other momentum space, 3
+// lattice (the square lattice, or the ring with importance sampling); plus 4
+// with early compression
+int variant(int model, int M, int N, int W, double g, int flags)
 {
-    const int base = model == FQ_MOM1D ? (M <= 16 ? 1 : 2) : (model == FQ_REAL2D || g != 0.0) ? 3 : 0;
+    const int base = model == FQ_MOM1D ? ((W == 1 && N + M - 1 <= 31) ? 1 : 2)
+                                       : (model == FQ_REAL2D || g != 0.0) ? 3 : 0;
     return base + ((flags & FQ_FLAG_EARLY_COMPRESSION) ? 4 : 0);
 }
 
@@ -309,9 +311,9 @@ size_t lds_bytes(int W, int slots)
 }
 
 // spawn kernel: three 32-bit words per table entry (unit offset, count word,
-// permutation), the scratch words, the 2048-byte select table and the coarse
-// parent index
-size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048 + sizeof(int) * SPAWN_COARSE; }
+// permutation), the scratch words, the 2048-byte select table, the coarse
+// parent index of the exact parents and the pair table of the momentum draw
+size_t lds_spawn_bytes(i64 cap_t) { return (size_t)cap_t * 12 + 160 * 8 + 2048 + sizeof(int) * SPAWN_COARSE + 2 * TRI_N; }
 
 constexpr size_t LDS_MAX = 160 * 1024;
 static_assert(sizeof(Ctrl) % 4 == 0, "Ctrl is copied in 32-bit words");
@@ -805,8 +807,8 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     for (int k = 0; k < R.nsq; k++) sq[k] = std::sqrt((double)k);
     for (int j = 0; j < h->M && j < MOM_MAXM; j++)
         eps[j] = (-2.0 * h->t) * std::cos((2.0 * 3.14159265358979323846 * (double)j) / (double)h->M);
-    const void *km = step_kernel(R.W, variant(h->model, h->M, h->g, p->flags), R.block, false);
-    const void *ks = step_kernel(R.W, variant(h->model, h->M, h->g, p->flags), R.spawn_block, true);
+    const void *km = step_kernel(R.W, variant(h->model, h->M, h->N, R.W, h->g, p->flags), R.block, false);
+    const void *ks = step_kernel(R.W, variant(h->model, h->M, h->N, R.W, h->g, p->flags), R.spawn_block, true);
     // lattice neighbours (sites x + lx y; +x, -x, +y, -y) and the
     // importance-sampling factors gz[N + k] = exp(-(g u) k), k = -N .. N
     const int lx = h->model == FQ_REAL2D ? h->lx : h->M, ly = h->M / lx;
@@ -839,7 +841,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
     Exec &X = q->X;
     X.W = R.W;
-    X.var = variant(h->model, h->M, h->g, p->flags);
+    X.var = variant(h->model, h->M, h->N, R.W, h->g, p->flags);
     X.block = R.block;
     X.spawn_block = R.spawn_block;
     X.lds_m = lds_bytes(R.W, R.slots);
@@ -990,7 +992,7 @@ static int load_state(fq_handle *q, const u64 *sa, const double *sv, i64 n, doub
     int *rn = rb + REFCAP;
     u64 r0 = ref_addr[0], r1 = W == 2 ? ref_addr[1] : 0;
 #define REFK(W_, M_) hipLaunchKernelGGL((k_ref<W_, M_>), dim3(1), dim3(64), 0, s, (const Inst *)q->d_inst, r0, r1, ra, rh, rb, rn, REFCAP)
-    const int vm = variant(q->h.model, q->h.M, q->h.g, 0);
+    const int vm = variant(q->h.model, q->h.M, q->h.N, W, q->h.g, 0);
     if (W == 1) { if (vm == 0) REFK(1, 0); else if (vm == 3) REFK(1, 3); else REFK(1, 1); }
     else { if (vm == 0) REFK(2, 0); else if (vm == 3) REFK(2, 3); else REFK(2, 1); }
 #undef REFK
@@ -1450,7 +1452,8 @@ int batch_plan(int n, const fq_hamiltonian *h, const fq_params *p, const fq_layo
         int rc = resolve(&h[i], &p[i], &lay[i], R, L, err);
         if (rc) { err = "batch instance " + std::to_string(i) + ": " + err; return rc; }
         if (i == 0) R0 = R;
-        if (R.W != R0.W || variant(h[i].model, h[i].M, h[i].g, p[i].flags) != variant(h[0].model, h[0].M, h[0].g, p[0].flags) ||
+        if (R.W != R0.W || variant(h[i].model, h[i].M, h[i].N, p[i].addr_words, h[i].g, p[i].flags) !=
+                                   variant(h[0].model, h[0].M, h[0].N, p[0].addr_words, h[0].g, p[0].flags) ||
             R.block != R0.block ||
             R.spawn_block != R0.spawn_block || R.slots != R0.slots) {
             err = "batch instance " + std::to_string(i) +
@@ -1833,6 +1836,64 @@ int fq_batch_run_spectral(fq_batch *b, int64_t n_steps, fq_step_stats *stats, vo
     return rc;
 }
 
+int fq_batch_autotune(fq_batch *b, const fq_layout *cand, int32_t n, int32_t trial_steps, void *scratch,
+                      size_t scratch_bytes, double *ms, int32_t *best, void *stream)
+{
+    if (!b || !cand || n < 1 || trial_steps < 1 || !scratch || !ms || !best) return FQ_EINVAL;
+    const int ni = (int)b->inst.size();
+    for (int j = 0; j < ni; j++)
+        if (!b->inst[j]->have_state) { b->err = "batch autotune: instance " + std::to_string(j) + " has no state"; return FQ_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<fq_hamiltonian> h(ni);
+    std::vector<fq_params> p(ni);
+    std::vector<fq_layout> lay(ni);
+    for (int j = 0; j < ni; j++) {
+        h[j] = b->inst[j]->h;
+        p[j] = b->inst[j]->p;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        b->err = "batch autotune: hipEventCreate failed";
+        if (e0) hipEventDestroy(e0);
+        return FQ_EHIP;
+    }
+    *best = -1;
+    double tbest = 0.0;
+    for (int i = 0; i < n; i++) {
+        ms[i] = -1.0;
+        // each instance keeps its capacities and takes the candidate's shared
+        // shape; the bucket count follows from the capacities when 0
+        for (int j = 0; j < ni; j++) {
+            lay[j] = b->inst[j]->L;
+            lay[j].buckets = cand[i].buckets;
+            lay[j].lds_slots = cand[i].lds_slots;
+            lay[j].block = cand[i].block;
+            lay[j].spawn_block = cand[i].spawn_block;
+        }
+        size_t need = 0;
+        if (fq_batch_workspace_size(ni, h.data(), p.data(), lay.data(), &need) != FQ_OK || need > scratch_bytes) continue;
+        fq_batch *t = nullptr;
+        if (fq_batch_create(ni, h.data(), p.data(), lay.data(), scratch, scratch_bytes, &t) != FQ_OK) continue;
+        bool ok = true;
+        for (int j = 0; j < ni && ok; j++) ok = fq_copy_state(t->inst[j], b->inst[j], stream) == FQ_OK;
+        ok = ok && fq_batch_run(t, 1, nullptr, stream) == FQ_OK;
+        float el = 0.0f;
+        ok = ok && hipEventRecord(e0, s) == hipSuccess;
+        ok = ok && fq_batch_run(t, trial_steps, nullptr, stream) == FQ_OK;
+        ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&el, e0, e1) == hipSuccess;
+        if (ok) {
+            ms[i] = (double)el / (double)trial_steps;
+            if (*best < 0 || ms[i] < tbest) { *best = i; tbest = ms[i]; }
+        }
+        fq_batch_destroy(t);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (*best < 0) { b->err = "batch autotune: no candidate ran"; return FQ_EINVAL; }
+    return FQ_OK;
+}
+
 const char *fq_batch_last_error(const fq_batch *b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 int32_t fq_batch_failed(const fq_batch *b) { return b ? b->failed : -1; }
@@ -1985,8 +2046,8 @@ int fq_server_submit(fq_server *sv, const fq_hamiltonian *h, const fq_params *p,
     fq_layout lo;
     int rc = fq_workspace_size(&r.h, &r.p, &r.L, &bytes, &lo);
     if (rc) { sv->err = "submit: " + g_err; return rc; }
-    if (h->model == FQ_MOM1D && h->M > 16) {
-        sv->err = "submit: a momentum-space server takes M <= 16";
+    if (h->model == FQ_MOM1D && (p->addr_words != 1 || h->N + h->M - 1 > 31)) {
+        sv->err = "submit: a momentum-space server takes one-word addresses of at most 31 bits (N + M - 1 <= 31)";
         return FQ_EINVAL;
     }
     r.bytes = align256(bytes);

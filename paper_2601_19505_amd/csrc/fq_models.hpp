@@ -17,8 +17,8 @@
 //  [0, K/2] then [K+1, (K+M)/2], skipping {p, q}; value
 //  (coef * c_pq c_rs) * (sqrt(n_p (n_q - d_pq)) * sqrt((n_r + 1)(n_s + 1 + d_rs))).
 //  Stochastic picks: a removal pair uniform over the P pairs (through the
-//  sampling order of mom_stochastic), then a destination uniform over that
-//  pair's R(K); inverse probability P R.
+//  sampling order of mom_draw), then a destination uniform over that pair's
+//  R(K); inverse probability P R.
 //
 //  A momentum-space address is handled as bit strings: `st` marks the first
 //  bit of every run of ones (an occupied mode), the mode of a run starting at
@@ -246,43 +246,180 @@ __device__ __forceinline__ T mom_move_to(const ModelConst &C, T a, T z, int sp, 
     return d;
 }
 
+// What every stochastic draw of one momentum-space parent shares: the run
+// starts `st` (occupied modes), the separators `z`, the run starts `dpos`
+// of modes with n >= 2, o = occupied modes, D = doubly occupied modes and
+// P = C(o, 2) + D removal pairs.
+template <class T> struct MomCtx {
+    T a, st, z, dpos;
+    int o, D, P;
+};
+template <class T> __device__ __forceinline__ MomCtx<T> mom_ctx(const ModelConst &C, T a)
+{
+    MomCtx<T> x;
+    x.a = a;
+    x.st = run_starts(a);
+    x.z = ~a & mask_below<T>(C.nb);
+    x.o = popc(x.st);
+    x.dpos = x.st & shr(a, 1);
+    x.D = popc(x.dpos);
+    x.P = x.o * (x.o - 1) / 2 + x.D;
+    return x;
+}
+
 // One stochastic spawn of a momentum-space parent (Sec. 6.3, two-stage
 // sampler): w0 picks the removal pair uniformly over the P pairs through the
 // sampling order (first the pairs (p, p) of doubly occupied modes, p
 // ascending; then the pairs of the i-th and j-th occupied mode, i < j, at
 // index j(j-1)/2 + i), w1 picks one of the pair's R(K) destinations in column
-// order.  Returns the destination, its matrix element h and qnum = P R, the
-// inverse generation probability.  No data-dependent branches, so the lanes
+// order.  Returns the destination, its matrix element h and R; the inverse
+// generation probability is P R.  No data-dependent branches, so the lanes
 // of a wave stay converged.
 template <class T>
-__device__ __forceinline__ T mom_stochastic(const ModelConst &C, T a, u32 w0, u32 w1, double &h, i64 &qnum,
-                                            const unsigned char *lut)
+__device__ __forceinline__ T mom_draw(const ModelConst &C, const MomCtx<T> &x, u32 w0, u32 w1, double &h, int &R,
+                                      const unsigned char *lut)
 {
     const int M = C.M;
-    const T st = run_starts(a);
-    const T z = ~a & mask_below<T>(C.nb);
-    const int o = popc(st);
-    const T dpos = st & shr(a, 1);  // run starts of modes with n >= 2
-    const int D = popc(dpos);
-    const int P = o * (o - 1) / 2 + D;
-    const int pi = (int)pick(w0, (u32)P);
-    const bool diag = pi < D;
-    const int t = diag ? 0 : pi - D;
+    const T a = x.a;
+    const int pi = (int)pick(w0, (u32)x.P);
+    const bool diag = pi < x.D;
+    const int t = diag ? 0 : pi - x.D;
     // j = largest integer with j (j - 1) / 2 <= t; the float root is exact to
     // within one and corrected
     int j = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
     j -= (j * (j - 1) / 2 > t) ? 1 : 0;
     j += ((j + 1) * j / 2 <= t) ? 1 : 0;
     const int i = t - j * (j - 1) / 2;
-    const T x = diag ? dpos : st;
-    const int sp = select_lut(x, diag ? pi : i, lut);
-    const int sq = select_lut(x, diag ? pi : j, lut);
+    const T xs = diag ? x.dpos : x.st;
+    const int sp = select_lut(xs, diag ? pi : i, lut);
+    const int sq = select_lut(xs, diag ? pi : j, lut);
     const int p = sp - popc(a & mask_below<T>(sp));
     const int q = sq - popc(a & mask_below<T>(sq));
     const int K = mod_add(p, q, M);
-    const int R = mom_R(K, M);
-    qnum = (i64)P * R;
-    return mom_move_to(C, a, z, sp, sq, p, q, K, (int)pick(w1, (u32)R), h, lut);
+    R = mom_R(K, M);
+    return mom_move_to(C, a, x.z, sp, sq, p, q, K, (int)pick(w1, (u32)R), h, lut);
+}
+
+// ---- momentum space, addresses of at most 31 bits
+//
+// The same draw as mom_draw for a parent whose address fits 31 bits, with
+// what every draw of the parent shares computed once: byte-prefix popcounts
+// of the run starts, of the doubly occupied run starts and of the mode
+// starts (so each select is a lookup), and a table `tri` of the pair (i, j),
+// i < j, at sampling index j (j - 1) / 2 + i.  With 31 bits every shift
+// count stays below 32.
+
+// byte k of the result: set bits of w in bytes 0 .. k
+__device__ __forceinline__ u32 byte_prefix(u32 w)
+{
+    u32 c = w - ((w >> 1) & 0x55555555u);
+    c = (c & 0x33333333u) + ((c >> 2) & 0x33333333u);
+    c = (c + (c >> 4)) & 0x0f0f0f0fu;
+    return c * 0x01010101u;
+}
+// position of the j-th set bit of w (w has more than j), given
+// pre = byte_prefix(w)
+__device__ __forceinline__ int select_pre(u32 w, u32 pre, int j, const unsigned char *lut)
+{
+    u32 jj = (u32)(j + 1);
+    jj |= jj << 8;
+    jj |= jj << 16;
+    const u32 ge = ((pre | 0x80808080u) - jj) & 0x80808080u;
+    const u32 b8 = 8u * (u32)(4 - __popc(ge));          // 8 x (bytes whose prefix is <= j)
+    const u32 before = __builtin_amdgcn_ubfe(pre << 8, b8, 8);  // set bits below that byte
+    return (int)b8 + lut[__builtin_amdgcn_ubfe(w, b8, 8) * 8u + ((u32)j - before)];
+}
+// remove bit x / insert a one at bit x (x <= 31): the bits below x stay,
+// the bits above move down / up by one
+__device__ __forceinline__ u32 del_bit32(u32 a, int x)
+{
+    const u32 m = (1u << x) - 1u;
+    return (a & m) | ((a >> 1) & ~m);
+}
+__device__ __forceinline__ u32 ins_one32(u32 a, int x)
+{
+    const u32 m = (1u << x) - 1u;
+    return (a & m) | (((a << 1) | (1u << x)) & ~m);
+}
+// ones starting at bit s of a 31-bit word (s <= 31)
+__device__ __forceinline__ int runlen31(u32 a, int s) { return __builtin_ctz(~(a >> s)); }
+
+struct MomCtx32 {
+    u32 a, st, dpos, ms;  // ms: bit j set at the start of mode j, shifted up by one
+    u32 pst, pdpos, pms;  // byte_prefix of st, dpos, ms
+    int D, P;
+};
+__device__ __forceinline__ MomCtx32 mom_ctx32(const ModelConst &C, u32 a)
+{
+    MomCtx32 x;
+    x.a = a;
+    x.st = a & ~(a << 1);
+    x.dpos = x.st & (a >> 1);
+    // a separator at bit p starts the next mode at p + 1, and mode 0 starts
+    // at bit 0: with ms = (separators << 1) | 1, mode j starts at the j-th
+    // set bit of ms
+    x.ms = ((~a & ((1u << C.nb) - 1u)) << 1) | 1u;
+    x.pst = byte_prefix(x.st);
+    x.pdpos = byte_prefix(x.dpos);
+    x.pms = byte_prefix(x.ms);
+    const int o = (int)(x.pst >> 24);
+    x.D = (int)(x.pdpos >> 24);
+    x.P = o * (o - 1) / 2 + x.D;
+    return x;
+}
+// tri[t] = i | j << 8 for the pair (i, j), i < j, of sampling index
+// t = j (j - 1) / 2 + i; t < nt
+constexpr int TRI_N = 512;  // pairs of up to 32 occupied modes
+__device__ __forceinline__ void tri_fill(unsigned short *tri, int tid, int nthreads)
+{
+    for (int t = tid; t < TRI_N; t += nthreads) {
+        // j = largest integer with j (j - 1) / 2 <= t: the float root is
+        // exact to within one and corrected
+        int j = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+        j -= (j * (j - 1) / 2 > t) ? 1 : 0;
+        j += ((j + 1) * j / 2 <= t) ? 1 : 0;
+        tri[t] = (unsigned short)((t - j * (j - 1) / 2) | (j << 8));
+    }
+}
+__device__ __forceinline__ u32 mom_draw31(const ModelConst &C, const MomCtx32 &x, u32 w0, u32 w1, double &h, int &R,
+                                          const unsigned char *lut, const unsigned short *tri)
+{
+    const int M = C.M;
+    const u32 a = x.a;
+    const int pi = (int)pick(w0, (u32)x.P);
+    const bool diag = pi < x.D;
+    const u32 ij = tri[diag ? 0 : pi - x.D];
+    const int i = diag ? pi : (int)(ij & 0xffu), j = diag ? pi : (int)(ij >> 8);
+    const u32 xs = diag ? x.dpos : x.st, pxs = diag ? x.pdpos : x.pst;
+    const int sp = select_pre(xs, pxs, i, lut);
+    const int sq = select_pre(xs, pxs, j, lut);
+    const int p = sp - __popc(a & ((1u << sp) - 1u));
+    const int q = sq - __popc(a & ((1u << sq) - 1u));
+    const int K = mod_add(p, q, M);
+    R = mom_R(K, M);
+    const int di = (int)pick(w1, (u32)R);
+    // destination pair (r, s) of index di in column order (r over [0, K/2],
+    // then over [K+1, (K+M)/2], skipping r = p)
+    const int half = (int)((u32)K >> 1);
+    const int idxp = p <= half ? p : half + 1 + (p - K - 1);
+    const int idx = di < idxp ? di : di + 1;
+    const int r = idx <= half ? idx : K + 1 + (idx - half - 1);
+    int s = K - r;
+    if (s < 0) s += M;
+    const int sr = select_pre(x.ms, x.pms, r, lut);
+    const int ss = select_pre(x.ms, x.pms, s, lut);
+    const int np = runlen31(a, sp), nq = runlen31(a, sq), nr = runlen31(a, sr), ns = runlen31(a, ss);
+    const int A = np * (nq - (p == q ? 1 : 0));
+    const int B = (nr + 1) * (ns + 1 + (r == s ? 1 : 0));
+    const int cc = (p == q ? 1 : 2) * (r == s ? 1 : 2);
+    h = (C.coef * (double)cc) * (gmem(C.sq)[A] * gmem(C.sq)[B]);
+    u32 d = del_bit32(a, sq);
+    d = del_bit32(d, sp);
+    const int r2 = sr - (p < r ? 1 : 0) - (q < r ? 1 : 0);
+    const int s2 = ss - (p < s ? 1 : 0) - (q < s ? 1 : 0);
+    d = ins_one32(d, max(r2, s2));
+    d = ins_one32(d, min(r2, s2));
+    return d;
 }
 
 // Entry e (0 <= e < m) of the column of a momentum-space parent in column

@@ -4,8 +4,10 @@
 //   table[p]: B buckets x cap_t entries, struct of arrays: address word 0,
 //             address word 1 (W = 2), value (f64); count per bucket.
 //   slab[p]:  B buckets x cap_s spawn records (array of structs: address
-//             words + value, 16 B for W = 1, 24 B for W = 2); count per bucket.
-// An address lives in bucket hash(address) >> (64 - log2 B).
+//             words + value; 12 B when the address fits 32 bits, else 16 B
+//             for W = 1, 24 B for W = 2); count per bucket.
+// An address lives in bucket bucket_index(address): the top log2 B bits of
+// a hash of the address.
 //
 // Step n -> n+1 for bucket b (Sec. 3.2; the two phases of the paper's
 // segmented product in Sec. 6.4 become one pass per bucket):
@@ -17,18 +19,21 @@
 //   3. projected energy: the entries of the reference column that live in
 //      this bucket are looked up in the LDS hash;
 //   4. compact survivors into table[1-p] and into LDS;
-//   5. spawn for step n+2 from every survivor: exact columns when
-//      |c| >= t_rel m, else ceil|c| Philox picks; attempts are expanded over
-//      the workgroup by a prefix sum over 4-attempt units.  Records are
-//      partitioned in rounds: every thread generates one unit into
-//      registers, takes a rank inside its destination group with an LDS
-//      atomic, one global atomic per group reserves a contiguous run, and
-//      the records are stored into the runs.  With B <= 64 the groups are
-//      the buckets of slab[1-p]; otherwise they are G coarse groups and the
-//      partition kernel splits every group into its B/G buckets.
+//   5. spawn for step n+2 from every survivor (a separate kernel): exact
+//      columns when |c| >= t_rel m, attempt by attempt over the workgroup;
+//      else ceil|c| Philox picks, in units of up to 8 attempts of one parent
+//      per thread.  Records are partitioned in rounds: every thread holds
+//      its round's records in registers, takes a rank inside each record's
+//      destination group with an LDS atomic, one global atomic per group
+//      reserves a contiguous run, and the records are stored into the runs.
+//      With B <= 64 the groups are the buckets of slab[1-p]; otherwise they
+//      are G coarse groups and the partition kernel splits every group into
+//      its B/G buckets.
 // A separate one-workgroup kernel reduces the per-bucket partial statistics,
 // performs the shift update (Eq. shift-update) and writes the statistics row.
 #pragma once
+#include <type_traits>
+
 #include "fq_models.hpp"
 
 namespace fq {
@@ -421,7 +426,7 @@ __device__ __forceinline__ void spawn_info(const Inst &I, typename AddrOf<W>::T 
     i64 m;
     if (MODEL == 0) m = 2 * popc(run_starts(a));
     else if (MODEL == 3) m = I.mc.ndir * popc(run_starts(a));
-    else if (W == 1 && I.mc.nb <= 32) m = mom_col_size<u32>(I.mc, (u32)word0(a));
+    else if (MODEL == 1 || (W == 1 && I.mc.nb <= 32)) m = mom_col_size<u32>(I.mc, (u32)word0(a));
     else m = mom_col_size(I.mc, a);
     double ac = fabs(c);
     exact = (m == 0) || ac >= I.t_rel * (double)m;
@@ -466,7 +471,7 @@ template <int W, bool COUNT> struct SpawnOut {
         if ((int)threadIdx.x < G) gcnt()[threadIdx.x] = 0;
         __syncthreads();
     }
-    __device__ int group(const T &d) const { return (int)(bucket_of(addr_hash(d), I.log2B) >> gshift); }
+    __device__ int group(const T &d) const { return (int)(bucket_index(d, I.log2B, I.mc.nb <= 32) >> gshift); }
     __device__ int rank(int g) const { return atomicAdd(&gcnt()[g], 1); }
     __device__ void reserve() const
     {
@@ -505,38 +510,37 @@ template <int W, bool COUNT> struct SpawnOut {
     }
 };
 
-// Spawns of all entries (Sec. 3.2, matrix compression; Sec. 7.1, exact
-// columns): an exact entry has m attempts, attempt k being column entry k; a
-// stochastic entry has ceil|c| attempts, each an independent draw.  The A
-// attempts of the nS entries (permuted indices w0_ .. w0_+nS-1, exact entries
-// first, attempt offsets in info[2 w], count word with the exact flag in
-// info[2 w + 1]) are enumerated flat: in each round thread t takes attempts
-// base + r BS + t (r < NR), finds each attempt's parent by a binary search
-// over the short range a coarse index of the bucket leaves and generates the record with branch-free
-// code, so all lanes of a wave do the same work (only the one round that
-// holds the boundary mixes the two kinds).  NR records per thread and round
-// make the runs appended to each destination group longer.
+// Spawns of the exact parents (Sec. 7.1, exact columns): an exact parent
+// with column size m has m attempts, attempt k being column entry k with
+// weight 1.  The A attempts of the nX exact parents (permuted indices
+// 0 .. nX-1, attempt offsets in info[2 w], count word in info[2 w + 1]) are
+// enumerated flat: in each round thread t takes attempts base + r BS + t
+// (r < NR), finds each attempt's parent by a binary search over the short
+// range a coarse index of the bucket leaves, and computes the column entry
+// directly (no walk of the column).  NR records per thread and round make
+// the runs appended to each destination group longer.
 #ifndef FQ_SPAWN_NR
 #define FQ_SPAWN_NR 4
 #endif
 constexpr int SPAWN_COARSE = 512;  // entries of the coarse parent index of a bucket
 
 template <int W, int MODEL, int BS, bool EARLY>
-__device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const int b, const int par,
-                                           const u32 spawn_step, const int w0_, const int nS, const u32 *info,
-                                           const u32 *perm, const i64 A, const unsigned char *lut, int *coarse)
+__device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const int b, const int par,
+                                            const u32 spawn_step, const int nX, const u32 *info, const u32 *perm,
+                                            const i64 A, const unsigned char *lut, int *coarse)
 {
     typedef typename AddrOf<W>::T T;
     constexpr int NR = FQ_SPAWN_NR;
     const int tid = threadIdx.x;
     const SpawnOut<W, EARLY> out(I, L, par, b);
-    const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
+    // the address fits 32 bits (same for every lane; always for model variant 1)
+    const bool narrow = MODEL == 1 || (W == 1 && I.mc.nb <= 32);
     // Coarse index: coarse[j] is the parent of attempt j 2^cs (the last entry
     // whose first attempt is at or before it), for j < nc.  The parent of
     // attempt k then lies between coarse[k >> cs] and the next coarse entry,
     // a short range searched per attempt.
     int top = 1;
-    while (2 * top <= nS) top *= 2;
+    while (2 * top <= nX) top *= 2;
     int cs = 5;
     while ((A >> cs) >= SPAWN_COARSE) cs++;
     const int nc = (int)(A >> cs) + 1;
@@ -545,7 +549,7 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
         int lo = 0;
         for (int stp = top; stp > 0; stp >>= 1) {
             const int nx = lo + stp;
-            if (nx < nS && info[2 * (w0_ + nx)] <= kj) lo = nx;
+            if (nx < nX && info[2 * nx] <= kj) lo = nx;
         }
         coarse[j] = lo;
     }
@@ -570,74 +574,36 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
                 // A < 2^32 (checked by the caller): 32-bit offsets suffice
                 const u32 k32 = (u32)kf;
                 const int j = (int)(kf >> cs);
-                int lo = coarse[j], hi = j + 1 < nc ? coarse[j + 1] : nS - 1;
+                int lo = coarse[j], hi = j + 1 < nc ? coarse[j + 1] : nX - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (info[2 * (w0_ + mid)] <= k32) lo = mid;
+                    if (info[2 * mid] <= k32) lo = mid;
                     else hi = mid - 1;
                 }
-                const int w = w0_ + lo;
+                const int w = lo;
                 const u32 k = k32 - info[2 * w];
-                const u32 cw = info[2 * w + 1];
-                const u32 cnt = cw & 0x7fffffffu;
                 const i64 e = (i64)b * I.cap_t + perm[w];
                 const u64 a0 = gmem(I.tab_a[par][0])[e];
                 const u64 a1 = W == 2 ? gmem(I.tab_a[par][1])[e] : 0;
                 const double c = gmem(I.tab_v[par])[e];
                 const T a = AddrOf<W>::make(a0, a1);
-                double h, q;
+                double h;
                 T dd;
-                if (cw >> 31) {
-                    // exact column (Sec. 7.1): attempt k is column entry k, weight 1
-                    if (MODEL == 0) {
-                        const T st = run_starts(a);
-                        dd = real_entry(I.mc, a, st, popc(st), (int)k, h);
-                    } else if (MODEL == 3) {
-                        const T st = run_starts(a);
-                        int kd;
-                        dd = lat_entry(I.mc, a, st, popc(st), (int)k, h, kd, lut);
-                        h = h * gmem(I.mc.gz)[I.mc.N + kd];
-                    } else if (narrow) {
-                        dd = AddrOf<W>::make((u64)mom_column_entry<u32>(I.mc, (u32)a0, (int)k, h, lut), 0);
-                    } else {
-                        dd = mom_column_entry(I.mc, a, (int)k, h, lut);
-                    }
-                    d[r] = dd;
-                    v[r] = (-(I.dtau * h)) * c;
-                } else {
                 if (MODEL == 0) {
-                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
-                    const u32 k3 = k & 3;
-                    const u32 rw = k3 == 0 ? rr.x : k3 == 1 ? rr.y : k3 == 2 ? rr.z : rr.w;
                     const T st = run_starts(a);
-                    const int o = popc(st);
-                    dd = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)(2 * o)), h);
-                    q = (double)(2 * o) / (double)cnt;
+                    dd = real_entry(I.mc, a, st, popc(st), (int)k, h);
                 } else if (MODEL == 3) {
-                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 2);
-                    const u32 k3 = k & 3;
-                    const u32 rw = k3 == 0 ? rr.x : k3 == 1 ? rr.y : k3 == 2 ? rr.z : rr.w;
                     const T st = run_starts(a);
-                    const int o = popc(st);
-                    const int m = I.mc.ndir * o;
                     int kd;
-                    dd = lat_entry(I.mc, a, st, o, (int)pick(rw, (u32)m), h, kd, lut);
+                    dd = lat_entry(I.mc, a, st, popc(st), (int)k, h, kd, lut);
                     h = h * gmem(I.mc.gz)[I.mc.N + kd];
-                    q = (double)m / (double)cnt;
+                } else if (narrow) {
+                    dd = AddrOf<W>::make((u64)mom_column_entry<u32>(I.mc, (u32)a0, (int)k, h, lut), 0);
                 } else {
-                    const R4 rr = draw(I.seed, a0, a1, spawn_step, 0u, k >> 1);
-                    const bool odd = (k & 1) != 0;
-                    const u32 x0 = odd ? rr.z : rr.x, x1 = odd ? rr.w : rr.y;
-                    i64 qn;
-                    if (narrow)
-                        dd = AddrOf<W>::make((u64)mom_stochastic<u32>(I.mc, (u32)a0, x0, x1, h, qn, lut), 0);
-                    else
-                        dd = mom_stochastic(I.mc, a, x0, x1, h, qn, lut);
-                    q = (double)qn / (double)cnt;
+                    dd = mom_column_entry(I.mc, a, (int)k, h, lut);
                 }
                 d[r] = dd;
-                v[r] = ((-(I.dtau * h)) * c) * q;
-                }
+                v[r] = (-(I.dtau * h)) * c;
                 pa0[r] = a0;
                 pa1[r] = a1;
                 kk[r] = k;
@@ -655,6 +621,173 @@ __device__ __forceinline__ void spawn_flat(const Inst &I, const Lds &L, const in
 #pragma unroll
         for (int r = 0; r < NR; r++)
             if (g[r] >= 0) out.put(g[r], rk[r], d[r], v[r], pa0[r], pa1[r], kk[r]);
+    }
+}
+
+// Spawns of the stochastic parents (Sec. 3.2, Eqs. spawning and
+// column-compression): a parent with ceil|c| = n attempts draws n column
+// entries independently, attempt k from its Philox block (k >> 1 in
+// momentum space, two words per attempt; k >> 2 otherwise, one word).  The
+// attempts are cut into units of U = SPAWN_UNIT consecutive attempts:
+// parent w has floor(n / U) full units (attempts U j .. U j + U - 1) and,
+// when U does not divide n, one partial unit with the last n mod U
+// attempts.  Units are
+// enumerated full units first (flat over the parents, unit offsets in
+// info[2 w]), then the partial units in the order of the parents
+// w = w0 .. w0 + nP - 1, which the caller sorted by n mod U descending, so
+// that the lanes of a wave run loops of equal length.  Each thread takes
+// one unit per round: it finds and loads the parent once, prepares what
+// every draw of that parent shares (run starts, pair counts, the weight
+// m / n or the two values of P R / n), computes each Philox block once for
+// the attempts that share it, and generates the unit's records.
+#ifndef FQ_SPAWN_UNIT
+#define FQ_SPAWN_UNIT 4
+#endif
+constexpr int SPAWN_UNIT = FQ_SPAWN_UNIT;
+// a unit starts at an attempt that is a multiple of SPAWN_UNIT, and the
+// draws of a unit assume that its Philox blocks start with it: four
+// attempts per block in real space, two in momentum space
+static_assert(SPAWN_UNIT % 4 == 0, "units must align with the Philox blocks");
+
+template <int W, int MODEL, int BS, bool EARLY>
+__device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const int b, const int par,
+                                            const u32 spawn_step, const int w0, const int nS, const int nP,
+                                            const u32 *info, const u32 *perm, const i64 FU,
+                                            const unsigned char *lut, const unsigned short *tri)
+{
+    typedef typename AddrOf<W>::T T;
+    // records of model variant 1 (addresses of at most 31 bits) are held as
+    // 32-bit words until they are stored
+    constexpr bool R32 = MODEL == 1 && W == 1;
+    typedef typename std::conditional<R32, u32, T>::type RA;
+    auto wide = [](RA x) -> T {
+        if constexpr (R32) return AddrOf<W>::make((u64)x, 0ull);
+        else return x;
+    };
+    constexpr int U = SPAWN_UNIT;
+    const int tid = threadIdx.x;
+    const SpawnOut<W, EARLY> out(I, L, par, b);
+    const int ns = nS - w0;  // stochastic parents
+    int top = 1;
+    while (2 * top <= ns) top *= 2;
+    const i64 NU = FU + nP;
+    for (i64 ubase = 0; ubase < NU; ubase += BS) {
+        out.begin();
+        RA d[U];
+        double v[U];
+        int gr[U];  // destination group << 16 | rank inside the round (ranks < BS U <= 8192), -1 if none
+        u64 pa0 = 0, pa1 = 0;
+        u32 k0 = 0;
+        int size = 0;
+#pragma unroll
+        for (int i = 0; i < U; i++) {
+            d[i] = RA{};
+            v[i] = 0.0;
+            gr[i] = -1;
+        }
+        const i64 u = ubase + tid;
+        int w = -1;
+        if (u < FU) {
+            // the last stochastic parent whose first full unit is at or before u
+            // (FU < 2^29: 32-bit offsets suffice)
+            const u32 u32_ = (u32)u;
+            int lo = w0;
+            for (int stp = top; stp > 0; stp >>= 1) {
+                const int nx = lo + stp;
+                if (nx < nS && info[2 * nx] <= u32_) lo = nx;
+            }
+            w = lo;
+            k0 = (u32)U * (u32_ - info[2 * w]);
+            size = U;
+        } else if (u < NU) {
+            w = w0 + (int)(u - FU);
+            const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
+            k0 = cnt & ~(u32)(U - 1);
+            size = (int)(cnt & (u32)(U - 1));
+        }
+        if (w >= 0) {
+            const u32 cnt = info[2 * w + 1] & 0x7fffffffu;
+            const i64 e = (i64)b * I.cap_t + perm[w];
+            pa0 = gmem(I.tab_a[par][0])[e];
+            pa1 = W == 2 ? gmem(I.tab_a[par][1])[e] : 0;
+            const double c = gmem(I.tab_v[par])[e];
+            const T a = AddrOf<W>::make(pa0, pa1);
+            const double cn = (double)cnt;
+            if constexpr (MODEL == 0 || MODEL == 3) {
+                const T st = run_starts(a);
+                const int o = popc(st);
+                const int m = (MODEL == 0 ? 2 : I.mc.ndir) * o;
+                const double q = (double)m / cn;
+                R4 rr;
+#pragma unroll
+                for (int i = 0; i < U; i++) {
+                    if (i < size) {
+                        if ((i & 3) == 0) rr = draw(I.seed, pa0, pa1, spawn_step, 0u, (k0 + (u32)i) >> 2);
+                        const u32 rw = (i & 3) == 0 ? rr.x : (i & 3) == 1 ? rr.y : (i & 3) == 2 ? rr.z : rr.w;
+                        double h;
+                        if constexpr (MODEL == 0) {
+                            d[i] = real_entry(I.mc, a, st, o, (int)pick(rw, (u32)m), h);
+                        } else {
+                            int kd;
+                            d[i] = lat_entry(I.mc, a, st, o, (int)pick(rw, (u32)m), h, kd, lut);
+                            h = h * gmem(I.mc.gz)[I.mc.N + kd];
+                        }
+                        v[i] = ((-(I.dtau * h)) * c) * q;
+                    }
+                }
+            } else if constexpr (R32) {
+                // momentum space, one-word addresses of at most 31 bits
+                const MomCtx32 x = mom_ctx32(I.mc, (u32)pa0);
+                const int hR = mom_R(0, I.mc.M);
+                const double qa = (double)((i64)x.P * hR) / cn, qb = (double)((i64)x.P * (hR - 1)) / cn;
+                R4 rr;
+#pragma unroll
+                for (int i = 0; i < U; i++) {
+                    if (i < size) {
+                        if ((i & 1) == 0) rr = draw(I.seed, pa0, 0ull, spawn_step, 0u, (k0 + (u32)i) >> 1);
+                        const u32 x0 = (i & 1) ? rr.z : rr.x, x1 = (i & 1) ? rr.w : rr.y;
+                        double h;
+                        int R;
+                        d[i] = mom_draw31(I.mc, x, x0, x1, h, R, lut, tri);
+                        v[i] = ((-(I.dtau * h)) * c) * (R == hR ? qa : qb);
+                    }
+                }
+            } else {
+                const MomCtx<T> x = mom_ctx<T>(I.mc, a);
+                const int hR = mom_R(0, I.mc.M);
+                const double qa = (double)((i64)x.P * hR) / cn, qb = (double)((i64)x.P * (hR - 1)) / cn;
+                R4 rr;
+#pragma unroll
+                for (int i = 0; i < U; i++) {
+                    if (i < size) {
+                        if ((i & 1) == 0) rr = draw(I.seed, pa0, pa1, spawn_step, 0u, (k0 + (u32)i) >> 1);
+                        const u32 x0 = (i & 1) ? rr.z : rr.x, x1 = (i & 1) ? rr.w : rr.y;
+                        double h;
+                        int R;
+                        d[i] = mom_draw<T>(I.mc, x, x0, x1, h, R, lut);
+                        v[i] = ((-(I.dtau * h)) * c) * (R == hR ? qa : qb);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < U; i++) {
+                if (i < size) {
+                    if (EARLY && fabs(v[i]) < I.theta) {
+                        const u32 k = k0 + (u32)i;
+                        const R4 rc = draw(I.seed, pa0, pa1, spawn_step, 4u + (k >> 28), k & 0x0fffffffu);
+                        v[i] = compress1(v[i], I.theta, rc.x);
+                    }
+                    if (!EARLY || v[i] != 0.0) {
+                        const int g = out.group(wide(d[i]));
+                        gr[i] = (g << 16) | out.rank(g);
+                    }
+                }
+            }
+        }
+        out.reserve();
+#pragma unroll
+        for (int i = 0; i < U; i++)
+            if (gr[i] >= 0) out.put(gr[i] >> 16, gr[i] & 0xffff, wide(d[i]), v[i], pa0, pa1, k0 + (u32)i);
     }
 }
 
@@ -710,7 +843,8 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
         }
     };
     const int out_par = 1 - p;
-    const bool narrow = W == 1 && I.mc.nb <= 32;  // the address fits 32 bits (same for every lane)
+    // the address fits 32 bits (same for every lane; always for model variant 1)
+    const bool narrow = MODEL == 1 || (W == 1 && I.mc.nb <= 32);
     const int spt = slots / BS;  // candidate slots per thread (contiguous), <= 8
 
     // candidate survivors of this thread: address words and value (0 = none)
@@ -985,47 +1119,79 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     u32 *perm = info + 2 * I.cap_t;
     unsigned char *lut = (unsigned char *)(perm + I.cap_t);  // select table, 2048 bytes
     for (int i = tid; i < 2048; i += BS) lut[i] = select_lut_entry(i);
+    // then the coarse parent index of the exact parents and the pair table
+    if (MODEL == 1 || MODEL == 2)
+        tri_fill((unsigned short *)(lut + 2048 + sizeof(int) * SPAWN_COARSE), tid, BS);
     const int nS = I.tab_n[par][b];
     const i64 tb = (i64)b * I.cap_t;
     const int chunk = (nS + BS - 1) / BS;
     const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
-    int n_ex = 0, bad = 0;
+    // order classes: 0 exact parents, then the stochastic parents by n mod U
+    // descending (U = SPAWN_UNIT; class U - (n mod U) for n mod U > 0, class
+    // U for n mod U = 0); ranks inside a class come from LDS counters (the
+    // order inside a class does not matter)
+    int *cls = (int *)(L.misc + 20);  // [0..8] counts, [9..18] offsets, [19..27] fill
+    if (tid < 28) cls[tid] = 0;
+    int bad = 0;
     for (int i = i0; i < i1; i++) {
         const T a = AddrOf<W>::make(gmem(I.tab_a[par][0])[tb + i], W == 2 ? gmem(I.tab_a[par][1])[tb + i] : 0);
         u32 cnt;
         bool ex;
         spawn_info<W, MODEL>(I, a, gmem(I.tab_v[par])[tb + i], cnt, ex, bad);
         info[2 * i] = cnt | (ex ? 0x80000000u : 0u);
-        n_ex += ex ? 1 : 0;
     }
     if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
+    __syncthreads();
     mark(5);
-    i64 tot_e;
-    i64 be = block_excl_scan<BS>(n_ex, L.misc, tot_e);
-    i64 bs_ = (i64)i0 - be;  // stochastic entries before this thread's chunk
-    for (int i = i0; i < i1; i++) {
-        const u32 ce = info[2 * i];
-        const int w = (ce >> 31) ? (int)be++ : (int)(tot_e + bs_++);
-        perm[w] = (u32)i;
-        info[2 * w + 1] = ce;
-    }
+    auto cls_of = [](u32 cw) -> int {
+        const u32 r = cw & (u32)(SPAWN_UNIT - 1);
+        return (cw >> 31) ? 0 : (r ? 1 + (SPAWN_UNIT - 1) - (int)r : SPAWN_UNIT);
+    };
+    for (int i = i0; i < i1; i++) atomicAdd(&cls[cls_of(info[2 * i])], 1);
+    __syncthreads();
     if (tid == 0) {
+        int o = 0;
+        for (int k = 0; k <= SPAWN_UNIT; k++) {
+            cls[9 + k] = o;
+            o += cls[k];
+        }
+        cls[9 + SPAWN_UNIT + 1] = o;
         L.misc[60] = 0;  // spawn records emitted by this bucket
         if (b == 0) ctrl->spawn_par = par;
     }
     __syncthreads();
-    // attempt offsets over all entries in the exact-first order
-    i64 atot;
+    for (int i = i0; i < i1; i++) {
+        const u32 ce = info[2 * i];
+        const int k = cls_of(ce);
+        const int w = cls[9 + k] + atomicAdd(&cls[19 + k], 1);
+        perm[w] = (u32)i;
+        info[2 * w + 1] = ce;
+    }
+    const int tot_e = cls[9 + 1];                  // exact parents: w < tot_e
+    const int nP = cls[9 + SPAWN_UNIT] - tot_e;   // stochastic parents with a partial unit
+    i64 sum_r = 0;
+    for (int k = 1; k < SPAWN_UNIT; k++) sum_r += (i64)cls[k] * (SPAWN_UNIT - k);
+    __syncthreads();
+    // offsets in the new order: attempt offsets of the exact parents (low 32
+    // bits) and full-unit offsets of the stochastic parents (high 32 bits)
+    i64 packed;
     {
-        i64 atts = 0;
-        for (int i = i0; i < i1; i++) atts += info[2 * i + 1] & 0x7fffffffu;
-        i64 ab = block_excl_scan<BS>(atts, L.misc, atot);
+        i64 x = 0;
         for (int i = i0; i < i1; i++) {
-            info[2 * i] = (u32)ab;
-            ab += info[2 * i + 1] & 0x7fffffffu;
+            const u32 cw = info[2 * i + 1], cnt = cw & 0x7fffffffu;
+            x += (cw >> 31) ? (i64)cnt : ((i64)(cnt / SPAWN_UNIT) << 32);
+        }
+        const i64 ab = block_excl_scan<BS>(x, L.misc, packed);
+        u32 ae = (u32)ab, fu = (u32)(ab >> 32);
+        for (int i = i0; i < i1; i++) {
+            const u32 cw = info[2 * i + 1], cnt = cw & 0x7fffffffu;
+            if (cw >> 31) { info[2 * i] = ae; ae += cnt; }
+            else { info[2 * i] = fu; fu += cnt / SPAWN_UNIT; }
         }
     }
-    if (atot >= ((i64)1 << 32)) {
+    const i64 A_ex = packed & 0xffffffffll, FU = packed >> 32;
+    const i64 atot = A_ex + (i64)SPAWN_UNIT * FU + sum_r;
+    if (atot >= ((i64)1 << 32) || A_ex >= ((i64)1 << 31)) {
         if (tid == 0) set_error(ctrl, FQE_CAP_SLAB, b);
         return;
     }
@@ -1039,8 +1205,9 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     if (!EARLY && tid == 0) I.spart[spawn_step & 1][b] = sp;
     __syncthreads();
     mark(6);
-    spawn_flat<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, 0, nS, info, perm, atot, lut,
-                                    (int *)(lut + 2048));
+    spawn_exact<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, tot_e, info, perm, A_ex, lut, (int *)(lut + 2048));
+    spawn_units<W, MODEL, BS, EARLY>(I, L, b, par, spawn_step, tot_e, nS, nP, info, perm, FU, lut,
+                                     (const unsigned short *)(lut + 2048 + sizeof(int) * SPAWN_COARSE));
     if (EARLY) {
         __syncthreads();
         if (tid == 0) {
@@ -1096,7 +1263,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             lb[e] = -1;
             if (i < n) {
                 load_rec<W>(I.rec, src, i, a0[e], a1[e], v[e]);
-                lb[e] = (int)(bucket_of(addr_hash(AddrOf<W>::make(a0[e], a1[e])), I.log2B) & (u32)(F - 1));
+                lb[e] = (int)(bucket_index(AddrOf<W>::make(a0[e], a1[e]), I.log2B, I.mc.nb <= 32) & (u32)(F - 1));
             }
         }
 #pragma unroll

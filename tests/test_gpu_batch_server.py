@@ -129,18 +129,20 @@ def _mean_loop(x):
     return acc / len(x)
 
 
-def test_server_alone_equals_mix():
+def test_server_alone_equals_mix(orc):
     """Requests admitted over several ticks under a pool that cannot hold all
-    of them at once: every result equals the solo run of that request."""
+    of them at once: every result equals the solo run of that request, and
+    the oracle's run of the same request (last statistics row bit for bit,
+    the means over the second half of the steps)."""
     fq = _fq()
     rng = np.random.default_rng(3)
     reqs = []
     for k in range(7):
         M = int(rng.integers(6, 11))
         sp = dict(model=0, M=M, N=M, t=1.0, u=float(rng.uniform(1, 10)), dtau=1e-3,
-                  target_walkers=float(rng.choice([1e3, 3e3, 1e4])), seed=500 + k,
+                  target_walkers=float(rng.choice([300.0, 1e3, 3e3])), seed=500 + k,
                   table_capacity=16384, spawn_capacity=131072)
-        reqs.append((sp, int(rng.integers(150, 700))))
+        reqs.append((sp, int(rng.integers(150, 500))))
     one = fq.workspace_size(*fq._ham_params(0, 10, 10), fq._layout(16384, 131072, 0, 1024, 256, 256))[0]
     pool = int(2.5 * one) + (1 << 20)  # the maps plus room for two resident solves
     sv = fq.Server(0, pool, lds_slots=1024, block=256, spawn_block=256, max_active=4,
@@ -167,20 +169,26 @@ def test_server_alone_equals_mix():
         assert ticks < 500
     _flush(f"[server] {len(reqs)} requests in {ticks} ticks, queue seen: {saw_queue}")
     assert saw_queue
-    for rid, (sp, n) in zip(ids, reqs):
-        info = sv.poll(rid)
+    infos = [sv.poll(rid) for rid in ids]
+    sv.close()
+    for info, (sp, n) in zip(infos, reqs):
         assert info["state"] == fq.REQ_DONE and info["steps_done"] == n
         solo = _solo(dict(sp, addr_words=1, **LAYOUT), n)
-        last = solo[-1]
-        for f in ("step", "len", "exact_steps", "inexact_steps", "spawns"):
-            assert info["last"][f] == int(last[f]), f
-        for f in ("shift", "norm", "hproj", "vproj"):
-            assert float(info["last"][f]).hex() == float(last[f]).hex(), f
-        tail = solo[solo["step"] * 2 > n]
-        assert info["n_mean"] == len(tail)
-        assert info["mean_shift"] == _mean_loop(tail["shift"])
-        assert info["mean_hproj"] == _mean_loop(tail["hproj"])
-    sv.close()
+        P = orc.params(0, sp["M"], sp["N"], 1.0, sp["u"], dtau=sp["dtau"], target=sp["target_walkers"],
+                       seed=sp["seed"])
+        a = orc.start_address(0, sp["M"], sp["N"])
+        ost, _, _ = orc.run(P, [a], [10.0], 0.0, 1, n, a, 10.0)
+        for ref in (solo, ost):
+            last = ref[-1]
+            for f in ("step", "len", "exact_steps", "inexact_steps", "spawns"):
+                assert info["last"][f] == int(last[f]), f
+            for f in ("shift", "norm", "hproj", "vproj"):
+                assert float(info["last"][f]).hex() == float(last[f]).hex(), f
+            tail = ref[ref["step"] * 2 > n]
+            assert info["n_mean"] == len(tail)
+            assert info["mean_shift"] == _mean_loop(tail["shift"])
+            assert info["mean_hproj"] == _mean_loop(tail["hproj"])
+            assert info["mean_vproj"] == _mean_loop(tail["vproj"])
 
 
 def test_copy_state_continues_identically():
@@ -224,3 +232,35 @@ def test_autotune_picks_a_candidate_and_leaves_source_unchanged():
     assert a.run(200).tobytes() == r2.tobytes()
     a.close()
     ref.close()
+
+
+def test_batch_autotune_picks_a_layout_and_leaves_batch_unchanged():
+    """fq_batch_autotune times shared layouts on device copies: the best
+    candidate is a valid one, an invalid candidate reads negative, the batch
+    continues exactly as an untouched twin, and a batch re-created with the
+    chosen layout from copied states continues identically too."""
+    fq = _fq()
+    specs = _real_specs()[:4]
+    twins = []
+    for _ in range(2):
+        b = fq.Batch(specs)
+        for i, sp in enumerate(specs):
+            a = fq.start_address(sp["model"], sp["M"], sp["N"])
+            b.instance(i).set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+        b.run(300)
+        twins.append(b)
+    cands = [dict(lds_slots=1024, block=256, spawn_block=256),
+             dict(lds_slots=2048, block=512, spawn_block=256),
+             dict(lds_slots=4096, block=1024, spawn_block=512),
+             dict(lds_slots=8192, block=256)]  # invalid: slots > 8 * block
+    ms, best = twins[0].autotune(cands, trial_steps=10)
+    _flush(f"[batch autotune] ms/step {ms}, best {best}")
+    assert best in (0, 1, 2) and ms[best] > 0 and ms[3] < 0
+    tb = fq.Batch([dict(sp, buckets=0, **cands[best]) for sp in specs])
+    for i in range(len(specs)):
+        tb.instance(i).copy_state_from(twins[0].instance(i))
+    ref = twins[1].run(200)
+    assert twins[0].run(200).tobytes() == ref.tobytes()
+    assert tb.run(200).tobytes() == ref.tobytes()
+    for b in twins + [tb]:
+        b.close()
