@@ -50,7 +50,7 @@ WORKLOADS = {
     "c2": dict(cfg="c2", name="real1d_M20_N20_u6_dtau1e-3_Nt1e7_W2",
                table_capacity=12_000_000, spawn_capacity=40_000_000, buckets=16384,
                lds_slots=2048, block=512, spawn_block=256, steps=1000),
-    "c2d": dict(cfg="c2d", name="real2d_6x6_N36_u1_t0.1_g1_dtau1e-2_Nt1e7_W2",
+    "c2d": dict(cfg="c2d", name="real2d_6x6_N36_u1_t0.1_g1_dtau1.5e-3_Nt1e7_W2",
                 table_capacity=30_000_000, spawn_capacity=60_000_000, buckets=16384,
                 lds_slots=2048, block=512, spawn_block=256, steps=2000),
     "c1": dict(cfg="c1", name="real1d_M6_N6_u6_dtau1e-3_Nt1e3",

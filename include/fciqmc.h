@@ -114,6 +114,18 @@ typedef struct {
  * flag skips the check, for callers who know their walkers never reach the
  * high-energy states the bound guards against. */
 #define FQ_FLAG_UNCHECKED_DTAU 64
+/* Initiator approximation (named in Sec. 1 and in the sign-problem paragraph
+ * of Sec. 3.2 with Cleland, Booth and Alavi cited; the paper does not state
+ * the rule, this is their original rule for real coefficients): an entry of
+ * c^(n) is an initiator when |c| > fq_params.initiator_threshold (n_a).  A
+ * spawn of a non-initiator counts only when its destination is an address of
+ * c^(n); otherwise it is discarded before annihilation.  Survivors and
+ * spawns of initiators always count; every address of c^(n) takes part in
+ * the merge even when its survivor is exactly 0, so the merged dump lists
+ * it.  Spawn events are generated, dumped and counted in `spawns` as without
+ * the rule.  n_a = 0 gives the plain step; n_a = +infinity never grows the
+ * support.  Creation fails with FQ_EINVAL when n_a is negative or NaN. */
+#define FQ_FLAG_INITIATOR 128
 /* Sampled dumps: with FQ_FLAG_DUMP_SAMPLE(k), k in 1..20, the dumps keep only
  * the spawn events whose destination, and the merged amplitudes whose
  * address, fall in a fixed sample of about 2^-k of all addresses (bits
@@ -126,11 +138,13 @@ typedef struct {
  * zeta^2/4 reproduce the paper's printed series); threshold: theta of the
  * vector compression (default 1); t_rel: semistochastic threshold, a column
  * is spawned exactly when |c| >= t_rel m (Sec. 7.1); seed: 64-bit seed of
- * the counter-based generator; addr_words: W. */
+ * the counter-based generator; addr_words: W; flags: FQ_FLAG_* bits;
+ * initiator_threshold: see FQ_FLAG_INITIATOR. */
 typedef struct {
     double dtau, target_walkers, zeta, xi, threshold, t_rel;
     uint64_t seed;
     int32_t addr_words, flags;
+    double initiator_threshold; /* n_a of FQ_FLAG_INITIATOR (ignored without it) */
 } fq_params;
 
 /* One row of the per-step time series (Sec. 4, the DataFrame columns):

@@ -24,6 +24,7 @@ FLAG_DUMP_MERGED = 2
 FLAG_PHASE_TIMING = 4
 FLAG_EARLY_COMPRESSION = 32
 FLAG_UNCHECKED_DTAU = 64
+FLAG_INITIATOR = 128
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ECAPACITY", -3: "EHIP", -4: "ENOMEM", -5: "EBUSY",
           -6: "EDIVERGED", -7: "ENOTFOUND"}
@@ -43,7 +44,8 @@ class Hamiltonian(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dtau", C.c_double), ("target_walkers", C.c_double), ("zeta", C.c_double),
                 ("xi", C.c_double), ("threshold", C.c_double), ("t_rel", C.c_double),
-                ("seed", C.c_uint64), ("addr_words", C.c_int32), ("flags", C.c_int32)]
+                ("seed", C.c_uint64), ("addr_words", C.c_int32), ("flags", C.c_int32),
+                ("initiator_threshold", C.c_double)]
 
 
 class Layout(C.Structure):
@@ -190,11 +192,16 @@ def _stream():
 
 
 def _ham_params(model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08, xi=None,
-                threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0, lx=0, g=0.0):
+                threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0, lx=0, g=0.0, initiator=None):
+    """`initiator`: threshold n_a of the initiator rule (sets FLAG_INITIATOR);
+    None leaves the rule off."""
     if xi is None:
         xi = zeta * zeta / 4.0
+    if initiator is not None:
+        flags |= FLAG_INITIATOR
     return (Hamiltonian(model, M, N, int(lx), float(t), float(u), float(g)),
-            Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words, flags))
+            Params(dtau, target_walkers, zeta, xi, threshold, t_rel, seed, addr_words, flags,
+                   0.0 if initiator is None else float(initiator)))
 
 
 def _layout(table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0,
@@ -208,12 +215,12 @@ class Solver:
     def __init__(self, model, M, N, t=1.0, u=1.0, dtau=1e-3, target_walkers=1000.0, zeta=0.08,
                  xi=None, threshold=1.0, t_rel=1.0, seed=0, addr_words=1, flags=0,
                  table_capacity=4096, spawn_capacity=16384, buckets=0, lds_slots=0, block=0,
-                 spawn_block=0, lx=0, g=0.0):
+                 spawn_block=0, lx=0, g=0.0, initiator=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the FCIQMC solver needs a GPU")
         self.ham, self.params = _ham_params(model, M, N, t, u, dtau, target_walkers, zeta, xi,
-                                            threshold, t_rel, seed, addr_words, flags, lx, g)
+                                            threshold, t_rel, seed, addr_words, flags, lx, g, initiator)
         self.W = addr_words
         nbytes, lay = workspace_size(self.ham, self.params,
                                      _layout(table_capacity, spawn_capacity, buckets, lds_slots,

@@ -300,13 +300,20 @@ int ilog2(i64 x)
 }
 
 // bytes per spawn record (see store_rec)
-size_t rec_bytes(int W, int nb) { return W == 2 ? 24 : (nb <= 32 ? 12 : 16); }
+// nb address bits, plus the non-initiator flag bit with the initiator rule
+size_t rec_bytes(int W, int nb, bool init) { return W == 2 ? 24 : (nb + (init ? 1 : 0) <= 32 ? 12 : 16); }
+
+// The non-initiator flag of a spawn record: the top bit of the last address
+// word as stored (bit 31 of a 12-byte record, bit 63 otherwise), above every
+// address bit; 0 without the initiator rule.
+u64 initiator_flag_bit(bool init, int rec) { return !init ? 0ull : rec == 12 ? (1ull << 31) : (1ull << 63); }
 
 // merge kernel: the LDS hash table (keys, 128-bit accumulators, W = 2 slot
-// states) and the scratch words
-size_t lds_bytes(int W, int slots)
+// states), the scratch words and, with the initiator rule, one occupancy
+// byte per slot
+size_t lds_bytes(int W, int slots, bool init)
 {
-    size_t per = 8 + (W == 2 ? 8 : 0) + 8 + 8 + (W == 2 ? 4 : 0);
+    size_t per = 8 + (W == 2 ? 8 : 0) + 8 + 8 + (W == 2 ? 4 : 0) + (init ? 1 : 0);
     return (size_t)slots * per + 160 * 8;
 }
 
@@ -333,6 +340,7 @@ struct Exec {
 
 struct Resolved {
     int W, nb, B, log2B, slots, block, spawn_block, two_pass, log2G, log2SUB;
+    bool init;  // the initiator rule
     i64 cap_t, cap_s, cap_c, dump_cap;
     size_t rec, slab_bytes;  // bytes per spawn record; bytes of one slab
     size_t off_ctrl, off_inst, off_iptr, off_pmap, off_sq, off_eps, off_nbr, off_gz, off_ref_a, off_ref_h, off_ref_b, off_ref_off, off_ref_tmp, off_ring,
@@ -380,6 +388,10 @@ int validate(const fq_hamiltonian *h, const fq_params *p, std::string &err)
         return FQ_EINVAL;
     }
     if (!std::isfinite(h->t) || !std::isfinite(h->u)) { err = "t and u must be finite"; return FQ_EINVAL; }
+    if ((p->flags & FQ_FLAG_INITIATOR) && !(p->initiator_threshold >= 0.0)) {
+        err = "initiator_threshold must be >= 0 (not NaN) with FQ_FLAG_INITIATOR";
+        return FQ_EINVAL;
+    }
     // Stability of the projector (Sec. 3.1): dtau < 2 / (E_max - E_0).
     const double width = spectral_width_bound(h);
     if (!(p->flags & FQ_FLAG_UNCHECKED_DTAU) && !(p->dtau * width < 2.0)) {
@@ -407,6 +419,7 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     L.spawn_capacity = std::max(L.spawn_capacity, L.table_capacity);
     R.W = p->addr_words;
     R.nb = h->N + h->M - 1;
+    R.init = (p->flags & FQ_FLAG_INITIATOR) != 0;
     if (L.lds_slots == 0) L.lds_slots = 4096;
     if (L.lds_slots < 1024 || L.lds_slots > 8192 || (L.lds_slots & (L.lds_slots - 1))) {
         err = "lds_slots must be a power of two in [1024, 8192]";
@@ -420,7 +433,7 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
         err = "spawn_block must be 256, 512 or 1024";
         return FQ_EINVAL;
     }
-    if (lds_bytes(R.W, L.lds_slots) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
+    if (lds_bytes(R.W, L.lds_slots, R.init) > LDS_MAX) { err = "LDS budget exceeded: lower lds_slots or block"; return FQ_EINVAL; }
     if (L.buckets == 0) {
         double uniq = (double)L.table_capacity + 0.25 * (double)L.spawn_capacity;
         i64 b = (i64)std::ceil(uniq / (0.55 * L.lds_slots));
@@ -457,7 +470,7 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     R.nsq = (h->N + 2) * (h->N + 2) + 8;
     // a slab also stages a whole table (8W + 8 bytes per entry) for
     // set_state, get_state and copy_state
-    R.rec = rec_bytes(R.W, R.nb);
+    R.rec = rec_bytes(R.W, R.nb, R.init);
     R.slab_bytes = std::max(R.rec * (size_t)R.B * R.cap_s, (size_t)(8 * R.W + 8) * (size_t)R.B * R.cap_t + 256);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
@@ -796,6 +809,8 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     I.log2SUB = R.log2SUB;
     I.cap_c = R.cap_c;
     I.rec = (int)R.rec;
+    I.iflag = initiator_flag_bit(R.init, I.rec);
+    I.n_a = R.init ? p->initiator_threshold : 0.0;
     I.coarse = q->ws + R.off_coarse;
     I.coarse_n = (int *)(q->ws + R.off_coarse_n);
     I.spart[0] = (SpawnPart *)(q->ws + R.off_spart[0]);
@@ -836,7 +851,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     if (e == hipSuccess && !pm.empty())
         e = hipMemcpy(q->ws + R.off_pmap, pm.data(), sizeof(u32) * pm.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: workspace initialisation"); delete q; return FQ_EHIP; }
-    e = ensure_lds(km, lds_bytes(R.W, R.slots));
+    e = ensure_lds(km, lds_bytes(R.W, R.slots, R.init));
     if (e == hipSuccess) e = ensure_lds(ks, lds_spawn_bytes(R.cap_t));
     if (e != hipSuccess) { hip_fail(q, e, "fq_create: hipFuncSetAttribute(step kernels)"); delete q; return FQ_EHIP; }
     Exec &X = q->X;
@@ -844,7 +859,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     X.var = variant(h->model, h->M, h->N, R.W, h->g, p->flags);
     X.block = R.block;
     X.spawn_block = R.spawn_block;
-    X.lds_m = lds_bytes(R.W, R.slots);
+    X.lds_m = lds_bytes(R.W, R.slots, R.init);
     X.lds_s = lds_spawn_bytes(R.cap_t);
     X.n = 1;
     X.insts = (const Inst *const *)(q->ws + R.off_iptr);
@@ -1304,12 +1319,13 @@ int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &e
     const int n = (int)hs.size();
     std::vector<const Inst *> ip(n);
     std::vector<u32> map, pmap;
-    size_t lds_s = 0;
+    size_t lds_s = 0, lds_m = 0;
     for (int i = 0; i < n; i++) {
         ip[i] = hs[i]->d_inst;
         for (int b = 0; b < hs[i]->R.B; b++) map.push_back(((u32)i << 14) | (u32)b);
         append_pmap(hs[i]->R, (u32)i, pmap);
         lds_s = std::max(lds_s, hs[i]->X.lds_s);
+        lds_m = std::max(lds_m, hs[i]->X.lds_m);
     }
     char *o = hdr;
     const Inst **d_ip = (const Inst **)o;
@@ -1333,6 +1349,7 @@ int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &e
     G.X.pmap = d_pmap;
     G.X.pgrid = (int)pmap.size();
     G.X.lds_s = lds_s;
+    G.X.lds_m = lds_m;
     G.ctrl.resize(n);
     return FQ_OK;
 }

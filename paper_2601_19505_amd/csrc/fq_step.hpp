@@ -112,6 +112,11 @@ struct Inst {
     int two_pass, log2G, log2SUB;
     int rec;  // bytes per spawn record: 12 (one address word that fits 32 bits), 16 or 24
     i64 cap_c;
+    // initiator rule: parents with |c| > n_a are initiators; a record of a
+    // non-initiator carries iflag (a bit above every address bit of the
+    // last address word); iflag = 0 without the rule
+    u64 iflag;
+    double n_a;
     char *coarse;
     int *coarse_n;
 };
@@ -258,6 +263,7 @@ struct Lds {
     u32 *state;     // W = 2 slot state: 0 empty, 1 busy, 2 full
     u64 *lo, *hi;   // fixed-point accumulators; later reused for survivors
     i64 *misc;      // scan scratch and block accumulators
+    unsigned char *occ;  // initiator rule: 1 where the slot holds an address of c^(n)
     int mask;
 };
 
@@ -417,6 +423,31 @@ __device__ __forceinline__ void lds_add_n(const Lds &L, const Inst &I, const u64
     }
 }
 
+// Initiator rule: add NB contributions of non-initiator parents (ok[e])
+// only onto addresses of c^(n).  Called after the table entries are in the
+// hash and L.occ marks them; every slot on the probe path of such an address
+// was full before any spawn record was inserted, so the lookup finds it
+// while other lanes insert concurrently, and a miss or an unmarked slot
+// means the destination is not occupied: the contribution is discarded.
+template <int W, int NB>
+__device__ __forceinline__ void lds_add_occupied(const Lds &L, const Inst &I, const u64 *a0, const u64 *a1,
+                                                 const double *v, const bool *ok, int b, int &inx)
+{
+#pragma unroll
+    for (int e = 0; e < NB; e++) {
+        if (!ok[e]) continue;
+        const int s = lds_find<W>(L, a0[e], a1[e], slot_hash(a0[e], W == 2 ? a1[e] : 0ull));
+        if (s < 0 || !L.occ[s]) continue;
+        u64 lo = 0, hi = 0;
+        int ovf = 0;
+        to_fixed(v[e], lo, hi, ovf, inx);
+        if (ovf) { set_error(I.ctrl, FQE_DIVERGED, b); continue; }
+        const u64 old = atomicAdd((unsigned long long *)&L.lo[s], (unsigned long long)lo);
+        const u64 h = hi + ((old + lo) < old ? 1ull : 0ull);
+        if (h) atomicAdd((unsigned long long *)&L.hi[s], (unsigned long long)h);
+    }
+}
+
 // ---------------------------------------------------------------- spawn info
 
 template <int W, int MODEL>
@@ -485,15 +516,19 @@ template <int W, bool COUNT> struct SpawnOut {
         }
         __syncthreads();
     }
-    __device__ void put(int g, int rk, const T &d, double v, u64 pa0, u64 pa1, u32 k) const
+    // ni: the parent is not an initiator; its flag I.iflag (0 without the
+    // initiator rule) goes into the record's address, not into the dump
+    __device__ void put(int g, int rk, const T &d, double v, u64 pa0, u64 pa1, u32 k, bool ni) const
     {
         const i64 pos = gbase()[g] + rk;
+        const u64 fl = ni ? I.iflag : 0ull;
+        const T df = AddrOf<W>::make(W == 1 ? word0(d) | fl : word0(d), W == 2 ? word1(d) | fl : 0ull);
         if (I.two_pass) {
             const i64 cs = ((i64)g << I.log2SUB) + sub;
-            if (pos < I.cap_c) store_rec<W>(I.rec, I.coarse, cs * I.cap_c + pos, d, v);
+            if (pos < I.cap_c) store_rec<W>(I.rec, I.coarse, cs * I.cap_c + pos, df, v);
             else set_error(I.ctrl, FQE_CAP_SLAB, g);
         } else {
-            if (pos < I.cap_s) store_rec<W>(I.rec, I.slab[out_par], (i64)g * I.cap_s + pos, d, v);
+            if (pos < I.cap_s) store_rec<W>(I.rec, I.slab[out_par], (i64)g * I.cap_s + pos, df, v);
             else set_error(I.ctrl, FQE_CAP_SLAB, g);
         }
         if ((I.flags & 1) && dump_keeps(I.flags, addr_hash(d))) {
@@ -560,6 +595,7 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
         double v[NR];
         int g[NR], rk[NR];
         u64 pa0[NR], pa1[NR];
+        bool ni[NR];
         u32 kk[NR];
 #pragma unroll
         for (int r = 0; r < NR; r++) {
@@ -569,6 +605,7 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
             g[r] = -1;
             rk[r] = 0;
             pa0[r] = pa1[r] = 0;
+            ni[r] = false;
             kk[r] = 0;
             if (kf < A) {
                 // A < 2^32 (checked by the caller): 32-bit offsets suffice
@@ -606,6 +643,7 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
                 v[r] = (-(I.dtau * h)) * c;
                 pa0[r] = a0;
                 pa1[r] = a1;
+                ni[r] = !(fabs(c) > I.n_a);
                 kk[r] = k;
                 if (EARLY && fabs(v[r]) < I.theta) {
                     const R4 rc = draw(I.seed, a0, a1, spawn_step, 4u + (k >> 28), k & 0x0fffffffu);
@@ -620,7 +658,7 @@ __device__ __forceinline__ void spawn_exact(const Inst &I, const Lds &L, const i
         out.reserve();
 #pragma unroll
         for (int r = 0; r < NR; r++)
-            if (g[r] >= 0) out.put(g[r], rk[r], d[r], v[r], pa0[r], pa1[r], kk[r]);
+            if (g[r] >= 0) out.put(g[r], rk[r], d[r], v[r], pa0[r], pa1[r], kk[r], ni[r]);
     }
 }
 
@@ -677,6 +715,7 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
         double v[U];
         int gr[U];  // destination group << 16 | rank inside the round (ranks < BS U <= 8192), -1 if none
         u64 pa0 = 0, pa1 = 0;
+        bool ni = false;
         u32 k0 = 0;
         int size = 0;
 #pragma unroll
@@ -713,6 +752,7 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
             const double c = gmem(I.tab_v[par])[e];
             const T a = AddrOf<W>::make(pa0, pa1);
             const double cn = (double)cnt;
+            ni = !(fabs(c) > I.n_a);
             if constexpr (MODEL == 0 || MODEL == 3) {
                 const T st = run_starts(a);
                 const int o = popc(st);
@@ -787,7 +827,7 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
         out.reserve();
 #pragma unroll
         for (int i = 0; i < U; i++)
-            if (gr[i] >= 0) out.put(gr[i] >> 16, gr[i] & 0xffff, wide(d[i]), v[i], pa0, pa1, k0 + (u32)i);
+            if (gr[i] >= 0) out.put(gr[i] >> 16, gr[i] & 0xffff, wide(d[i]), v[i], pa0, pa1, k0 + (u32)i, ni);
     }
 }
 
@@ -831,7 +871,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     L.hi = (u64 *)q; q += (size_t)slots * 8;
     L.state = (u32 *)q; if (W == 2) q += (size_t)slots * 4;
     L.misc = (i64 *)q; q += 160 * 8;
+    L.occ = (unsigned char *)q;  // slots bytes, present with the initiator rule only
     L.mask = slots - 1;
+    const bool init = I.iflag != 0;
 
     const bool timing = (I.flags & 4) != 0;
     u64 tprev = timing ? wall_clock64() : 0;
@@ -915,7 +957,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     if (EARLY && fabs(w) < I.theta)
                         w = compress1(w, I.theta, draw(I.seed, t0[e], t1[e], (u32)(n + 1), 2u, 0u).x);
                     tw[e] = w;
-                    tok[e] = w != 0.0;
+                    // with the initiator rule every address of c^(n) enters
+                    // the hash, even with a zero survivor: it is occupied
+                    tok[e] = w != 0.0 || init;
                 }
             }
             lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe, inx);
@@ -931,11 +975,26 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
             }
         }
         if (timing) { __syncthreads(); mark(1); }
+        if (init) {
+            // the hash now holds exactly the addresses of c^(n)
+            __syncthreads();
+            for (int s = tid; s < slots; s += BS) L.occ[s] = (W == 1 ? L.k0[s] != EMPTY : L.state[s] == 2u) ? 1 : 0;
+            __syncthreads();
+        }
         for (int i0 = 0; i0 < ns; i0 += MS * BS) {
-            bool xok[MS];
+            bool xok[MS], xni[MS];
 #pragma unroll
-            for (int e = 0; e < MS; e++) xok[e] = i0 + e * BS + tid < ns;
+            for (int e = 0; e < MS; e++) {
+                const bool in = i0 + e * BS + tid < ns;
+                // records of non-initiator parents carry I.iflag (0 without the rule)
+                const bool ni = in && ((W == 1 ? x0[e] : x1[e]) & I.iflag) != 0;
+                if (W == 1) x0[e] &= ~I.iflag;
+                else x1[e] &= ~I.iflag;
+                xok[e] = in && !ni;
+                xni[e] = ni;
+            }
             lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe, inx);
+            if (init) lds_add_occupied<W, MS>(L, I, x0, x1, xv, xni, b, inx);
             // next batch
 #pragma unroll
             for (int e = 0; e < MS; e++) {
@@ -1263,7 +1322,10 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             lb[e] = -1;
             if (i < n) {
                 load_rec<W>(I.rec, src, i, a0[e], a1[e], v[e]);
-                lb[e] = (int)(bucket_index(AddrOf<W>::make(a0[e], a1[e]), I.log2B, I.mc.nb <= 32) & (u32)(F - 1));
+                // the bucket of the address without the non-initiator flag
+                const typename AddrOf<W>::T a =
+                    AddrOf<W>::make(W == 1 ? a0[e] & ~I.iflag : a0[e], W == 2 ? a1[e] & ~I.iflag : 0ull);
+                lb[e] = (int)(bucket_index(a, I.log2B, I.mc.nb <= 32) & (u32)(F - 1));
             }
         }
 #pragma unroll

@@ -47,9 +47,9 @@ def test_encode_rejects_overflow():
 
 
 def _ws(model=0, M=6, N=6, W=1, lx=0, g=0.0, t=1.0, u=6.0, dtau=1e-3, target=1e3, theta=1.0,
-        flags=0, **kw):
+        flags=0, n_a=0.0, **kw):
     h = fq.Hamiltonian(model, M, N, lx, t, u, g)
-    p = fq.Params(dtau, target, 0.08, 0.0016, theta, 1.0, 0, W, flags)
+    p = fq.Params(dtau, target, 0.08, 0.0016, theta, 1.0, 0, W, flags, n_a)
     lay = fq.Layout(kw.get("table", 1000), kw.get("spawn", 4000), kw.get("buckets", 0),
                     kw.get("slots", 0), kw.get("block", 0), kw.get("spawn_block", 0))
     return fq.workspace_size(h, p, lay)
@@ -72,10 +72,21 @@ def test_workspace_size_and_defaults():
                                 dict(model=2, M=6, lx=6), dict(model=1, M=8, g=0.1),
                                 dict(g=float("nan")), dict(model=2, M=36, N=36, lx=6, W=1, u=1.0),
                                 dict(target=float("inf")), dict(target=0.0), dict(theta=float("nan")),
-                                dict(theta=0.0), dict(dtau=0.0), dict(dtau=float("inf"))])
+                                dict(theta=0.0), dict(dtau=0.0), dict(dtau=float("inf")),
+                                dict(flags=128, n_a=-1.0), dict(flags=128, n_a=float("nan"))])
 def test_workspace_size_rejects_invalid(kw):
     with pytest.raises(fq.FqError):
         _ws(**kw)
+
+
+def test_initiator_threshold_accepted():
+    """The initiator rule takes any n_a >= 0, infinity included; without
+    the flag the threshold is ignored."""
+    for n_a in (0.0, 3.0, float("inf")):
+        assert _ws(flags=fq.FLAG_INITIATOR, n_a=n_a)[0] > 0
+    assert _ws(n_a=-1.0)[0] > 0
+    # the flag bit sits above the 31 address bits of the momentum benchmark
+    assert _ws(model=1, M=16, N=16, flags=fq.FLAG_INITIATOR, n_a=3.0)[0] > 0
 
 
 def test_lattice_workspace_sizes():

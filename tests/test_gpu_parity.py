@@ -29,11 +29,12 @@ def _flush(*a):
 
 def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2048, block=512,
              t_rel=1.0, theta=1.0, step=6, shift=-1.3, sector=None, lo=0.05, hi=300.0, t=1.0,
-             spawn_block=None, early=False, lx=0, g=0.0):
+             spawn_block=None, early=False, lx=0, g=0.0, initiator=None):
     fq = _fq()
     spawn_block = block if spawn_block is None else spawn_block
     _flush(f"[one_step] model={model} M={M} N={N} lx={lx} g={g} W={W} n={n_entries} B={buckets} "
-           f"slots={slots} block={block} spawn_block={spawn_block} t_rel={t_rel} early={early}")
+           f"slots={slots} block={block} spawn_block={spawn_block} t_rel={t_rel} early={early} "
+           f"initiator={initiator}")
     rng = np.random.default_rng(seed)
     occs = synthetic.random_occupations(rng, M, N, n_entries, momentum_sector=sector)
     vals = synthetic.random_amplitudes(rng, len(occs), lo=lo, hi=hi)
@@ -42,14 +43,15 @@ def one_step(orc, model, M, N, u, dtau, n_entries, seed, W=1, buckets=4, slots=2
     assert np.array_equal(gaddr[:, 0], oaddr[:, 0])
     ref_o, ref_g = oaddr[0], gaddr[0]
     P = orc.params(model, M, N, t, u, dtau=dtau, target=1e4, theta=theta, t_rel=t_rel,
-                   seed=seed + 99, early=early, lx=lx, g=g)
+                   seed=seed + 99, early=early, lx=lx, g=g, initiator=initiator)
     o = orc.step(P, oaddr, vals, shift, step + 1, ref_o, 10.0, events=True, merged=True)
-    cap_t = max(4096, 4 * len(occs))
+    # room for the input and for the merged table of the step
+    cap_t = max(4096, 4 * len(occs), 2 * len(o["merged_addr"]))
     s = fq.Solver(model, M, N, t=t, u=u, dtau=dtau, target_walkers=1e4, threshold=theta,
                   t_rel=t_rel, seed=seed + 99, addr_words=W,
                   flags=3 | (fq.FLAG_EARLY_COMPRESSION if early else 0), table_capacity=cap_t,
                   spawn_capacity=max(8 * len(o["events"]), 65536), buckets=buckets,
-                  lds_slots=slots, block=block, spawn_block=spawn_block, lx=lx, g=g)
+                  lds_slots=slots, block=block, spawn_block=spawn_block, lx=lx, g=g, initiator=initiator)
     s.set_state(gaddr, vals, shift, step, ref=ref_g, yref=10.0)
     ev = s.spawn_dump()
     st = s.run(1)
@@ -332,3 +334,72 @@ def test_schedule_independence():
                                 (2, 2048, 1024, 256), (128, 1024, 256, 256)]:
         st = _c1_gpu(3000, B, slots, block, sb)
         assert st.tobytes() == ref.tobytes(), (B, slots, block, sb)
+
+
+INITIATOR_CASES = [
+    # model, M, N, lx, g, t, u, dtau, n, seed, W, buckets, slots, block, t_rel, early, n_a
+    (0, 8, 5, 0, 0.0, 1.0, 2.5, 1e-2, 600, 51, 1, 8, 2048, 512, 0.5, False, 20.0),
+    (0, 12, 12, 0, 0.0, 1.0, 6.0, 1e-3, 3000, 52, 2, 16, 4096, 1024, 1.0, False, 20.0),
+    # 32 address bits: 16-byte records, the flag in bit 63
+    (0, 20, 13, 0, 0.0, 1.0, 4.0, 1e-3, 2000, 53, 1, 16, 2048, 512, 1.0, False, 20.0),
+    # the momentum benchmark system (31 bits): 12-byte records, the flag in bit 31
+    (1, 16, 16, 0, 0.0, 1.0, 4.0, 5e-4, 3000, 54, 1, 64, 4096, 512, 1.0, False, 20.0),
+    (1, 8, 8, 0, 0.0, 1.0, 4.0, 1e-3, 1500, 55, 1, 8, 2048, 512, 1.0, False, 0.0),
+    (1, 7, 6, 0, 0.0, 1.0, 2.0, 1e-3, 400, 56, 2, 4, 2048, 256, 2.0, False, float("inf")),
+    # two-pass partition
+    (1, 10, 10, 0, 0.0, 1.0, 4.0, 1e-3, 2500, 57, 1, 128, 2048, 1024, 1.0, False, 30.0),
+    (0, 20, 20, 0, 0.0, 1.0, 6.0, 1e-3, 3000, 58, 2, 128, 2048, 1024, 1.0, False, 50.0),
+    # lattice, importance sampling, early compression
+    (2, 9, 9, 3, 0.5, 1.0, 2.0, 1e-3, 400, 59, 1, 4, 2048, 512, 1.0, False, 20.0),
+    (2, 36, 36, 6, 1.0, 0.1, 1.0, 1.5e-3, 3000, 60, 2, 128, 4096, 1024, 1.0, False, 20.0),
+    (0, 8, 8, 0, 0.0, 1.0, 3.0, 1e-3, 600, 61, 1, 8, 2048, 512, 1.0, True, 5.0),
+    (2, 9, 9, 3, 0.5, 1.0, 2.0, 1e-3, 400, 62, 1, 4, 2048, 512, 1.0, True, 5.0),
+]
+
+
+@pytest.mark.parametrize("case", INITIATOR_CASES,
+                         ids=lambda c: f"init_m{c[0]}_M{c[1]}N{c[2]}_W{c[10]}_B{c[11]}_e{int(c[15])}_na{c[16]}")
+def test_single_step_initiator_bit_exact(orc, case):
+    """Initiator rule (|c| > n_a; non-initiator spawns count only onto
+    addresses of c^(n)): spawn events, merged sums (every input address
+    included), the compressed state and the statistics equal the oracle's
+    bit for bit."""
+    model, M, N, lx, g, t, u, dtau, n, seed, W, B, slots, block, t_rel, early, n_a = case
+    r = one_step(orc, model, M, N, u, dtau, n, seed, W, B, slots, block, t_rel=t_rel, t=t, lx=lx, g=g,
+                 early=early, lo=0.05 if not early else 0.01, hi=300.0 if not early else 50.0, initiator=n_a)
+    check_parity(*r)
+    o, mg = r[0], r[3]
+    if 0.0 < n_a < float("inf"):
+        # the rule acted: some events of non-initiator parents reach an
+        # address outside c^(n) and are missing from the merged sums
+        merged = set(_key2(mg[0]))
+        missed = [e for e in o["events"] if (int(e["dest"][1]), int(e["dest"][0])) not in merged]
+        assert missed
+
+
+def test_initiator_trajectory_bit_exact_vs_oracle(orc):
+    """The 6/6 ring at u = 6 with the initiator rule at n_a = 3 for 3000
+    steps from one start address: every statistics row of the GPU run equals
+    the oracle's bit for bit."""
+    fq = _fq()
+    c = synthetic.CONFIGS["c1"]
+    steps = 3000
+    _flush(f"[initiator trajectory] {steps} steps")
+    s = fq.Solver(c["model"], c["M"], c["N"], t=c["t"], u=c["u"], dtau=c["dtau"],
+                  target_walkers=c["target"], seed=c["seed"], addr_words=1, table_capacity=1024,
+                  spawn_capacity=8192, initiator=3.0)
+    a = fq.start_address(c["model"], c["M"], c["N"])
+    s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    st = s.run(steps)
+    s.close()
+    P = orc.params(c["model"], c["M"], c["N"], c["t"], c["u"], dtau=c["dtau"], target=c["target"],
+                   seed=c["seed"], initiator=3.0)
+    oa = orc.start_address(c["model"], c["M"], c["N"])
+    ost, _, _ = orc.run(P, [oa], [10.0], 0.0, 1, steps, oa, 10.0)
+    for f in ost.dtype.names:
+        gv, ov = st[f], ost[f]
+        if gv.dtype.kind == "f":
+            bad = np.nonzero(gv.view(np.uint64) != ov.view(np.uint64))[0]
+        else:
+            bad = np.nonzero(gv != ov)[0]
+        assert len(bad) == 0, (f, bad[:5], gv[bad[:5]], ov[bad[:5]])

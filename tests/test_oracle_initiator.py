@@ -164,3 +164,23 @@ def test_occupied_address_with_a_zero_survivor(orc):
     assert len(cases) >= 5
     assert all(im[k] == pm[k] for k in cases)
     assert all(im[k] == pm.get(k, 0.0) for k in inputs)
+
+
+def test_bias_shrinks_as_the_walker_number_grows(orc):
+    """The 6/6 ring at u = 6 with n_a = 3: at N_t = 50 few entries exceed n_a
+    and the truncated spawning leaves a large positive energy bias; at
+    N_t = 1000 most of the weight sits on initiators and the bias falls by
+    more than a factor of ten (the plain step has none at either size)."""
+    from oracle import stats
+    M = N = 6
+    E0 = orc.eigs_sparse(orc.ham(0, M, N, 1.0, 6.0), 1)[0]
+    a = orc.start_address(0, M, N)
+    bias = {}
+    for Nt in (50.0, 1000.0):
+        P = orc.params(0, M, N, 1.0, 6.0, dtau=0.01, target=Nt, seed=7, initiator=3.0)
+        st, _, _ = orc.run(P, [a], [10.0], 0.0, 1, 12000, a, 10.0)
+        pe = stats.projected_energy(st["hproj"], st["vproj"], skip=3000)
+        bias[Nt] = (pe.ratio - E0, pe.err)
+    (b0, e0), (b1, e1) = bias[50.0], bias[1000.0]
+    assert b0 > 20 * e0 and b0 > 0.5
+    assert abs(b1) < 0.1 * b0
