@@ -52,19 +52,18 @@ __global__ __launch_bounds__(FIN_BS) void k_finalize(const Inst *const *insts)
 // runs that different workgroups append to one bucket's slab then meet in
 // that XCD's L2, which merges partial cache lines before they are written
 // back.
-#ifndef FQ_PART_BS
-#define FQ_PART_BS 1024
-#endif
-#ifndef FQ_PART_RPT
-#define FQ_PART_RPT 2
-#endif
-constexpr int PART_BS = FQ_PART_BS;    // threads per workgroup of the second pass
-constexpr int PART_RPT = FQ_PART_RPT;  // records per thread and round
+// Threads per workgroup and records per thread and round, by address
+// words (measured: 512 x 4 for the 12- and 16-byte records of one-word
+// addresses, 1024 x 2 for the 24-byte records of two-word addresses).
+template <int W> struct PartShape;
+template <> struct PartShape<1> { static constexpr int BS = 512, RPT = 4; };
+template <> struct PartShape<2> { static constexpr int BS = 1024, RPT = 2; };
 
-template <int W> __global__ __launch_bounds__(PART_BS) void k_part(const Inst *const *insts, const u32 *map)
+template <int W>
+__global__ __launch_bounds__(PartShape<W>::BS) void k_part(const Inst *const *insts, const u32 *map)
 {
     const u32 m = map[blockIdx.x];
-    partition_coarse<W, PART_BS, PART_RPT>(const_inst(insts[m >> 14]), (int)(m & 0x3fffu));
+    partition_coarse<W, PartShape<W>::BS, PartShape<W>::RPT>(const_inst(insts[m >> 14]), (int)(m & 0x3fffu));
 }
 
 // start of a chunk of steps: statistics rows are stored from row 0
@@ -551,8 +550,8 @@ hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s, hipEvent_t mid =
     hipError_t e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.spawn_block), args, X.lds_s, s);
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e == hipSuccess && X.pgrid > 0) {
-        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(PART_BS), 0, s, X.insts, X.pmap);
-        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(PART_BS), 0, s, X.insts, X.pmap);
+        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(PartShape<1>::BS), 0, s, X.insts, X.pmap);
+        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(PartShape<2>::BS), 0, s, X.insts, X.pmap);
         e = hipGetLastError();
     }
     return e;

@@ -839,6 +839,9 @@ __device__ __forceinline__ void spawn_units(const Inst &I, const Lds &L, const i
 #ifndef FQ_MERGE_MS
 #define FQ_MERGE_MS 2  // spawn records in flight per merge thread (and per batch of LDS inserts)
 #endif
+#ifndef FQ_MERGE_PREFETCH
+#define FQ_MERGE_PREFETCH 1  // load the next batch before inserting the current one
+#endif
 
 // Merge of bucket b for step n+1: the diagonal survivors of table[p] and the
 // spawn records of slab[p] are summed per address in an LDS hash table, the
@@ -854,13 +857,18 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     const int slots = I.slots;
     __shared__ int s_err;
 
+    // one memory round trip before the barrier: the halt state (thread 0),
+    // the step parameters and the counts of both parities (the kernel that
+    // ran before wrote them; nothing in this launch does)
     if (tid == 0) s_err = halted(ctrl);
-    __syncthreads();
-    if (s_err) return;
-
     const i64 n = ctrl->step;
     const int p = ctrl->parity;
     const double S = ctrl->shift;
+    const int tn0 = I.tab_n[0][b], tn1 = I.tab_n[1][b];
+    const int sn0 = I.slab_n[0][b], sn1 = I.slab_n[1][b];
+    const int r_beg = I.ref_off[b], r_end = I.ref_off[b + 1];  // this bucket's reference entries
+    __syncthreads();
+    if (s_err) return;
 
     // LDS carve-up
     Lds L;
@@ -900,9 +908,9 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
     {
         // ------------------------------------------------ 1. merge
         int nprobe = 0;
-        const int nt = I.tab_n[p][b];
+        const int nt = p ? tn1 : tn0;
         const i64 tb = (i64)b * I.cap_t;
-        const int ns = min(I.slab_n[p][b], (int)I.cap_s);
+        const int ns = min(p ? sn1 : sn0, (int)I.cap_s);
         const char *sb = I.slab[p] + (i64)b * I.cap_s * (i64)I.rec;
         // Loads in flight per thread: the first MT table entries and the
         // first MS spawn records are requested before the LDS hash is
@@ -962,15 +970,36 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                     tok[e] = w != 0.0 || init;
                 }
             }
-            lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe, inx);
-            // next batch
+            if (FQ_MERGE_PREFETCH) {
+                // the next batch is in flight while this one is inserted
+                u64 n0[MT], n1[MT];
 #pragma unroll
-            for (int e = 0; e < MT; e++) {
-                const int i = i0 + (MT + e) * BS + tid;
-                if (i < nt) {
-                    t0[e] = gmem(I.tab_a[p][0])[tb + i];
-                    t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
-                    tc[e] = gmem(I.tab_v[p])[tb + i];
+                for (int e = 0; e < MT; e++) {
+                    const int i = i0 + (MT + e) * BS + tid;
+                    n0[e] = n1[e] = 0;
+                    if (i < nt) {
+                        n0[e] = gmem(I.tab_a[p][0])[tb + i];
+                        n1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
+                        tc[e] = gmem(I.tab_v[p])[tb + i];
+                    }
+                }
+                lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe, inx);
+#pragma unroll
+                for (int e = 0; e < MT; e++) {
+                    t0[e] = n0[e];
+                    t1[e] = n1[e];
+                }
+            } else {
+                lds_add_n<W, MT>(L, I, t0, t1, tw, tok, b, nprobe, inx);
+                // next batch
+#pragma unroll
+                for (int e = 0; e < MT; e++) {
+                    const int i = i0 + (MT + e) * BS + tid;
+                    if (i < nt) {
+                        t0[e] = gmem(I.tab_a[p][0])[tb + i];
+                        t1[e] = W == 2 ? gmem(I.tab_a[p][1])[tb + i] : 0;
+                        tc[e] = gmem(I.tab_v[p])[tb + i];
+                    }
                 }
             }
         }
@@ -993,13 +1022,34 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
                 xok[e] = in && !ni;
                 xni[e] = ni;
             }
-            lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe, inx);
-            if (init) lds_add_occupied<W, MS>(L, I, x0, x1, xv, xni, b, inx);
-            // next batch
+            if (FQ_MERGE_PREFETCH) {
+                // the next batch is in flight while this one is inserted
+                u64 y0[MS], y1[MS];
+                double yv[MS];
 #pragma unroll
-            for (int e = 0; e < MS; e++) {
-                const int i = i0 + (MS + e) * BS + tid;
-                if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
+                for (int e = 0; e < MS; e++) {
+                    const int i = i0 + (MS + e) * BS + tid;
+                    y0[e] = y1[e] = 0;
+                    yv[e] = 0.0;
+                    if (i < ns) load_rec<W>(I.rec, sb, i, y0[e], y1[e], yv[e]);
+                }
+                lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe, inx);
+                if (init) lds_add_occupied<W, MS>(L, I, x0, x1, xv, xni, b, inx);
+#pragma unroll
+                for (int e = 0; e < MS; e++) {
+                    x0[e] = y0[e];
+                    x1[e] = y1[e];
+                    xv[e] = yv[e];
+                }
+            } else {
+                lds_add_n<W, MS>(L, I, x0, x1, xv, xok, b, nprobe, inx);
+                if (init) lds_add_occupied<W, MS>(L, I, x0, x1, xv, xni, b, inx);
+                // next batch
+#pragma unroll
+                for (int e = 0; e < MS; e++) {
+                    const int i = i0 + (MS + e) * BS + tid;
+                    if (i < ns) load_rec<W>(I.rec, sb, i, x0[e], x1[e], xv[e]);
+                }
             }
         }
         __syncthreads();
@@ -1048,6 +1098,7 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 #pragma unroll
         for (int k = 0; k < 8; k++)
             if (k < spt) L.lo[tid * spt + k] = dbits(rc[k]);
+        if (timing) __syncthreads();
         mark(3);
         // 128-bit accumulators: [40,41] norm, [42,43] y.Hc, [44,45] y.c;
         // [46] inexact flag of the bucket
@@ -1056,7 +1107,6 @@ __device__ void merge_bucket(const Inst &I, const int b, char *smem)
 
         // ------------------------------------------------ 3. projected energy
         {
-            const int r_beg = I.ref_off[b], r_end = I.ref_off[b + 1];
             for (int e = r_beg + tid; e < r_end; e += BS) {
                 u64 a0 = gmem(I.ref_a[0])[e];
                 u64 a1 = W == 2 ? gmem(I.ref_a[1])[e] : 0;
@@ -1152,11 +1202,14 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     const int tid = threadIdx.x;
     Ctrl *ctrl = I.ctrl;
     __shared__ int s_err;
+    // the halt state, the step parameters and both parities' table counts
+    // in one memory round trip before the barrier
     if (tid == 0) s_err = halted(ctrl);
-    __syncthreads();
-    if (s_err) return;
     const i64 n = ctrl->step;
     const int p = ctrl->parity;
+    const int tn0 = I.tab_n[0][b], tn1 = I.tab_n[1][b];
+    __syncthreads();
+    if (s_err) return;
     // mode 0 runs after the merge of step n+1 (state in table[1-p]), mode 1 on c^(n)
     const int par = mode == 0 ? 1 - p : p;
     const u32 spawn_step = (u32)(mode == 0 ? n + 2 : n + 1);
@@ -1181,7 +1234,7 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     // then the coarse parent index of the exact parents and the pair table
     if (MODEL == 1 || MODEL == 2)
         tri_fill((unsigned short *)(lut + 2048 + sizeof(int) * SPAWN_COARSE), tid, BS);
-    const int nS = I.tab_n[par][b];
+    const int nS = par ? tn1 : tn0;
     const i64 tb = (i64)b * I.cap_t;
     const int chunk = (nS + BS - 1) / BS;
     const int i0 = min(nS, tid * chunk), i1 = min(nS, i0 + chunk);
@@ -1192,12 +1245,29 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
     int *cls = (int *)(L.misc + 20);  // [0..8] counts, [9..18] offsets, [19..27] fill
     if (tid < 28) cls[tid] = 0;
     int bad = 0;
-    for (int i = i0; i < i1; i++) {
-        const T a = AddrOf<W>::make(gmem(I.tab_a[par][0])[tb + i], W == 2 ? gmem(I.tab_a[par][1])[tb + i] : 0);
-        u32 cnt;
-        bool ex;
-        spawn_info<W, MODEL>(I, a, gmem(I.tab_v[par])[tb + i], cnt, ex, bad);
-        info[2 * i] = cnt | (ex ? 0x80000000u : 0u);
+    // four entries at a time: their loads are in flight together
+    for (int i = i0; i < i1; i += 4) {
+        u64 e0[4], e1[4];
+        double ec[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            e0[k] = e1[k] = 0;
+            ec[k] = 0.0;
+            if (i + k < i1) {
+                e0[k] = gmem(I.tab_a[par][0])[tb + i + k];
+                e1[k] = W == 2 ? gmem(I.tab_a[par][1])[tb + i + k] : 0;
+                ec[k] = gmem(I.tab_v[par])[tb + i + k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i + k < i1) {
+                u32 cnt;
+                bool ex;
+                spawn_info<W, MODEL>(I, AddrOf<W>::make(e0[k], e1[k]), ec[k], cnt, ex, bad);
+                info[2 * (i + k)] = cnt | (ex ? 0x80000000u : 0u);
+            }
+        }
     }
     if (bad) set_error(ctrl, FQE_ATTEMPTS, b);
     __syncthreads();
