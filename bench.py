@@ -111,10 +111,14 @@ def measured_valu(fq, kernel):
     if not digest or digest[0] != fq.source_digest():
         return None
     for i, ln in enumerate(lines):
-        if ln.startswith("void " + kernel + "<") and i + 1 < len(lines):
-            nxt = lines[i + 1].split()
-            if nxt and nxt[0] == "SQ_INSTS_VALU":
-                return float(nxt[1])
+        if ln.startswith("void " + kernel + "<"):
+            # the counters of this kernel: indented lines up to the next kernel
+            for nx in lines[i + 1:]:
+                if not nx.startswith(" "):
+                    break
+                f = nx.split()
+                if f and f[0] == "SQ_INSTS_VALU":
+                    return float(f[1])
     return None
 
 
@@ -540,30 +544,53 @@ def blocked_error(x):
 
 def compression_study(fq, torch, steps=20000, skip=5000):
     """Statistical efficiency f = 1 / (sigma^2 Omega t) of the shift (Sec. 7.1)
-    for late and early compression on the real-space 12/12 ring (u = 6,
-    dtau = 1e-3, N_t = 1e4): sigma = blocked error of the mean shift, Omega =
-    steps after `skip`, t = GPU time per step from HIP events."""
-    out = {}
-    for name, flag in (("late", 0), ("early", fq.FLAG_EARLY_COMPRESSION)):
-        s = fq.Solver(fq.REAL1D, 12, 12, u=6.0, dtau=1e-3, target_walkers=1e4, seed=7, flags=flag,
-                      table_capacity=40000, spawn_capacity=200000)
-        a = fq.start_address(fq.REAL1D, 12, 12)
-        s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
-        s.run(skip)
-        s.set_timing(True)
-        s.kernel_time(reset=True)
-        st = s.run(steps)
-        kms, nl = s.kernel_time()
-        s.close()
-        t = sum(kms.values()) / 1e3 / max(nl, 1)
-        sig = blocked_error(st["shift"])
-        out[name] = dict(mean_shift=float(st["shift"].mean()), sigma=sig, steps=steps, s_per_step=t,
-                         f=1.0 / (sig * sig * steps * t), mean_len=float(st["len"].mean()),
-                         mean_spawns=float(st["spawns"].mean()))
-        log(f"[bench] compression {name}: shift {out[name]['mean_shift']:.5f} +- {sig:.5f}, "
-            f"{t * 1e3:.4f} ms/step, f {out[name]['f']:.4g}")
-    return dict(workload="real-space 1D Bose-Hubbard ring M = N = 12, u = 6, dtau = 1e-3, N_t = 1e4",
-                **out)
+    for late and early compression: sigma = blocked error of the mean shift,
+    Omega = timed steps, t = GPU time per step from HIP events.  Systems: C1
+    (the 6/6 ring, N_t = 1e3), the 12/12 ring of the paper's efficiency
+    figure (u = 6, N_t = 1e4) and C2 (the 20/20 ring with two address words,
+    N_t = 1e7, timed after the ramp)."""
+    c1, c2 = synthetic.CONFIGS["c1"], synthetic.CONFIGS["c2"]
+    systems = [
+        ("c1", "real-space ring M = N = 6, u = 6, dtau = 1e-3, N_t = 1e3 (C1)",
+         dict(model=c1["model"], M=c1["M"], N=c1["N"], u=c1["u"], dtau=c1["dtau"], target_walkers=c1["target"],
+              seed=c1["seed"], addr_words=c1["W"], table_capacity=4096, spawn_capacity=32768), None),
+        ("ring12", "real-space ring M = N = 12, u = 6, dtau = 1e-3, N_t = 1e4",
+         dict(model=fq.REAL1D, M=12, N=12, u=6.0, dtau=1e-3, target_walkers=1e4, seed=7,
+              table_capacity=40000, spawn_capacity=200000), None),
+        ("c2", "real-space ring M = N = 20, u = 6, dtau = 1e-3, N_t = 1e7, two address words (C2)",
+         dict(model=c2["model"], M=c2["M"], N=c2["N"], u=c2["u"], dtau=c2["dtau"], target_walkers=c2["target"],
+              seed=c2["seed"], addr_words=c2["W"], table_capacity=WORKLOADS["c2"]["table_capacity"],
+              spawn_capacity=WORKLOADS["c2"]["spawn_capacity"], buckets=WORKLOADS["c2"]["buckets"],
+              lds_slots=WORKLOADS["c2"]["lds_slots"], block=WORKLOADS["c2"]["block"],
+              spawn_block=WORKLOADS["c2"]["spawn_block"]), c2["target"]),
+    ]
+    res = {}
+    for key, desc, kw, ramp_to in systems:
+        out = {"workload": desc}
+        for name, flag in (("late", 0), ("early", fq.FLAG_EARLY_COMPRESSION)):
+            kw2 = dict(kw)
+            model, M, N = kw2.pop("model"), kw2.pop("M"), kw2.pop("N")
+            s = fq.Solver(model, M, N, flags=flag, **kw2)
+            a = fq.start_address(model, M, N, kw2.get("addr_words", 1))
+            s.set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+            if ramp_to is not None:
+                ramp(s, ramp_to, skip, f"compression {key} {name} ramp", chunk=500)
+            else:
+                s.run(skip)
+            s.set_timing(True)
+            s.kernel_time(reset=True)
+            st = s.run(steps)
+            kms, nl = s.kernel_time()
+            s.close()
+            t = sum(kms.values()) / 1e3 / max(nl, 1)
+            sig = blocked_error(st["shift"])
+            out[name] = dict(mean_shift=float(st["shift"].mean()), sigma=sig, steps=steps, s_per_step=t,
+                             f=1.0 / (sig * sig * steps * t), mean_len=float(st["len"].mean()),
+                             mean_norm=float(st["norm"].mean()), mean_spawns=float(st["spawns"].mean()))
+            log(f"[bench] compression {key} {name}: shift {out[name]['mean_shift']:.5f} +- {sig:.5f}, "
+                f"{t * 1e3:.4f} ms/step, f {out[name]['f']:.4g}")
+        res[key] = out
+    return res
 
 
 def ramp(s, target, settle, what, chunk=250, limit=60000):
