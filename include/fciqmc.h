@@ -170,7 +170,7 @@ typedef struct {
 
 /* Sizes of the device data structures.  table_capacity: largest number of
  * stored addresses; spawn_capacity: largest number of spawn events per step;
- * buckets: hash buckets (power of two, 0 = choose); lds_slots: LDS hash slots
+ * buckets: hash buckets (power of two <= 32768, 0 = choose); lds_slots: LDS hash slots
  * per bucket (power of two, 1024..8192, <= 8 * block, 0 = 4096); block:
  * threads per workgroup of the merge kernel (256, 512 or 1024; 0 = choose);
  * spawn_block: threads per workgroup of the spawn kernel (256, 512 or 1024;

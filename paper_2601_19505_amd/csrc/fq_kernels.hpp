@@ -10,15 +10,15 @@
 
 // // The step kernels run over a set of instances: one, or a batch.  `insts` is
 // a device array of instance descriptors.  A merge or spawn workgroup finds
-// its instance and bucket through `map` (entry = instance << 14 | bucket);
+// its instance and bucket through `map` (entry = instance << 15 | bucket);
 // without a map there is one instance and workgroup b takes bucket b.
 
 __device__ __forceinline__ const fq::Inst &locate(const fq::Inst *const *insts, const fq::u32 *map, int &b)
 {
     if (map) {
         const fq::u32 m = map[blockIdx.x];
-        b = (int)(m & 0x3fffu);
-        return fq::const_inst(insts[m >> 14]);
+        b = (int)(m & 0x7fffu);
+        return fq::const_inst(insts[m >> 15]);
     }
     b = (int)blockIdx.x;
     return fq::const_inst(insts[0]);

@@ -59,11 +59,14 @@ template <int W> struct PartShape;
 template <> struct PartShape<1> { static constexpr int BS = 512, RPT = 4; };
 template <> struct PartShape<2> { static constexpr int BS = 1024, RPT = 2; };
 
-template <int W>
+// FMAX: the most buckets per coarse group the workgroup splits into (256, or
+// 512 with more than 16384 buckets)
+template <int W, int FMAX>
 __global__ __launch_bounds__(PartShape<W>::BS) void k_part(const Inst *const *insts, const u32 *map)
 {
     const u32 m = map[blockIdx.x];
-    partition_coarse<W, PartShape<W>::BS, PartShape<W>::RPT>(const_inst(insts[m >> 14]), (int)(m & 0x3fffu));
+    partition_coarse<W, PartShape<W>::BS, PartShape<W>::RPT, FMAX>(const_inst(insts[m >> 14]),
+                                                                   (int)(m & 0x3fffu));
 }
 
 // start of a chunk of steps: statistics rows are stored from row 0
@@ -243,6 +246,7 @@ __global__ void k_set_i64(i64 *p, i64 v) { *p = v; }
 namespace {
 
 constexpr i64 RING = 4096;
+constexpr int MAX_BUCKETS = 32768;  // 15 bits of a workgroup map entry
 constexpr int NEV = 5;  // timing events per step: merge | spawn | partition | finalize
 constexpr int REFCAP = 1 << 15;
 
@@ -335,6 +339,7 @@ struct Exec {
     int grid = 0;
     const u32 *pmap = nullptr;    // second-pass partition map
     int pgrid = 0;
+    bool wide_groups = false;     // coarse groups of more than 256 buckets
 };
 
 struct Resolved {
@@ -438,9 +443,9 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
         i64 b = (i64)std::ceil(uniq / (0.55 * L.lds_slots));
         L.buckets = (int)((i64)1 << ilog2(std::max<i64>(b, 1)));
     }
-    if (L.buckets > 16384) L.buckets = 16384;
-    if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > 16384) {
-        err = "buckets must be a power of two <= 16384";
+    if (L.buckets > MAX_BUCKETS) L.buckets = MAX_BUCKETS;
+    if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > MAX_BUCKETS) {
+        err = "buckets must be a power of two <= 32768";
         return FQ_EINVAL;
     }
     R.B = L.buckets;
@@ -550,8 +555,15 @@ hipError_t launch_spawn(const Exec &X, int mode, hipStream_t s, hipEvent_t mid =
     hipError_t e = hipLaunchKernel(kf, dim3(X.grid), dim3(X.spawn_block), args, X.lds_s, s);
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e == hipSuccess && X.pgrid > 0) {
-        if (X.W == 1) hipLaunchKernelGGL(k_part<1>, dim3(X.pgrid), dim3(PartShape<1>::BS), 0, s, X.insts, X.pmap);
-        else hipLaunchKernelGGL(k_part<2>, dim3(X.pgrid), dim3(PartShape<2>::BS), 0, s, X.insts, X.pmap);
+        // groups of more than 256 buckets (more than 16384 buckets in all)
+        // take the kernel with the larger count arrays
+        if (X.W == 1) {
+            if (X.wide_groups) hipLaunchKernelGGL((k_part<1, 512>), dim3(X.pgrid), dim3(PartShape<1>::BS), 0, s, X.insts, X.pmap);
+            else hipLaunchKernelGGL((k_part<1, 256>), dim3(X.pgrid), dim3(PartShape<1>::BS), 0, s, X.insts, X.pmap);
+        } else {
+            if (X.wide_groups) hipLaunchKernelGGL((k_part<2, 512>), dim3(X.pgrid), dim3(PartShape<2>::BS), 0, s, X.insts, X.pmap);
+            else hipLaunchKernelGGL((k_part<2, 256>), dim3(X.pgrid), dim3(PartShape<2>::BS), 0, s, X.insts, X.pmap);
+        }
         e = hipGetLastError();
     }
     return e;
@@ -866,6 +878,7 @@ int fq_create(const fq_hamiltonian *h, const fq_params *p, const fq_layout *layo
     X.grid = R.B;
     X.pmap = (const u32 *)(q->ws + R.off_pmap);
     X.pgrid = (int)pm.size();
+    X.wide_groups = R.two_pass && R.log2B - R.log2G > 8;
     q->ring_host.resize(RING);
     *out = q;
     return FQ_OK;
@@ -1321,7 +1334,7 @@ int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &e
     size_t lds_s = 0, lds_m = 0;
     for (int i = 0; i < n; i++) {
         ip[i] = hs[i]->d_inst;
-        for (int b = 0; b < hs[i]->R.B; b++) map.push_back(((u32)i << 14) | (u32)b);
+        for (int b = 0; b < hs[i]->R.B; b++) map.push_back(((u32)i << 15) | (u32)b);
         append_pmap(hs[i]->R, (u32)i, pmap);
         lds_s = std::max(lds_s, hs[i]->X.lds_s);
         lds_m = std::max(lds_m, hs[i]->X.lds_m);
@@ -1347,6 +1360,8 @@ int group_build(Group &G, std::vector<fq_handle *> hs, char *hdr, std::string &e
     G.X.grid = (int)map.size();
     G.X.pmap = d_pmap;
     G.X.pgrid = (int)pmap.size();
+    // instances are sorted by bucket count: the first has the widest groups
+    G.X.wide_groups = hs[0]->X.wide_groups;
     G.X.lds_s = lds_s;
     G.X.lds_m = lds_m;
     G.ctrl.resize(n);
@@ -1994,7 +2009,7 @@ constexpr int SERVER_MAX_ACTIVE = 1024;
 
 size_t server_header_bytes(int max_active)
 {
-    return group_header_bytes(max_active, (i64)max_active * 16384, (i64)max_active * 4096);
+    return group_header_bytes(max_active, (i64)max_active * MAX_BUCKETS, (i64)max_active * 4096);
 }
 
 void retire(fq_server *sv, Req &r)

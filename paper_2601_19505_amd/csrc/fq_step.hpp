@@ -1357,18 +1357,20 @@ __device__ void spawn_bucket(const Inst &I, const int b, const int mode, char *s
 // LDS, so that consecutive lanes store consecutive records of one run (whole
 // cache lines instead of one scattered record per lane).  Releases the
 // coarse sub-slab.
-template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I, const int cs)
+template <int W, int BS, int RPT, int FMAX> __device__ void partition_coarse(const Inst &I, const int cs)
 {
-    static_assert(BS >= 256 && BS % 64 == 0, "the scan of the F <= 256 counts needs 256 threads");
+    static_assert(BS >= FMAX && BS % 64 == 0, "the scan of the F <= FMAX counts needs FMAX threads");
+    static_assert(FMAX == 256 || FMAX == 512, "groups of at most 256 or 512 buckets");
+    typedef typename std::conditional<FMAX <= 256, unsigned char, unsigned short>::type Dst;
     constexpr int NRND = BS * RPT;  // records per round
     __shared__ int s_err;
-    __shared__ int cnt[256];        // per bucket of the group: count, then run start in the sorted round
-    __shared__ int wsum[4];
-    __shared__ i64 off[256];        // reserved run start minus the run start in the sorted round
+    __shared__ int cnt[FMAX];       // per bucket of the group: count, then run start in the sorted round
+    __shared__ int wsum[FMAX / 64];
+    __shared__ i64 off[FMAX];       // reserved run start minus the run start in the sorted round
     __shared__ u64 st_a0[NRND];
     __shared__ u64 st_a1[W == 2 ? NRND : 1];
     __shared__ double st_v[NRND];
-    __shared__ unsigned char st_d[NRND];
+    __shared__ Dst st_d[NRND];
     Ctrl *ctrl = I.ctrl;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) s_err = halted(ctrl);
@@ -1377,7 +1379,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
     const int q = ctrl->spawn_par;
     const int g = cs >> I.log2SUB;
     const int log2F = I.log2B - I.log2G;
-    const int F = 1 << log2F;  // <= 256 (B <= 16384)
+    const int F = 1 << log2F;  // <= FMAX (the host picks FMAX from B / G)
     const int n = min(I.coarse_n[cs], (int)I.cap_c);
     const char *src = I.coarse + (i64)cs * I.cap_c * (i64)I.rec;
     for (int r0 = 0; r0 < n; r0 += NRND) {
@@ -1402,7 +1404,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
         for (int e = 0; e < RPT; e++)
             if (lb[e] >= 0) rk[e] = atomicAdd(&cnt[lb[e]], 1);
         __syncthreads();
-        // exclusive scan of the F counts (threads 0 .. F-1, at most four waves)
+        // exclusive scan of the F counts (threads 0 .. F-1, at most FMAX / 64 waves)
         const int c = tid < F ? cnt[tid] : 0;
         int x = c;
 #pragma unroll
@@ -1410,7 +1412,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             const int y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
-        if (lane == 63 && wid < 4) wsum[wid] = x;
+        if (lane == 63 && wid < FMAX / 64) wsum[wid] = x;
         __syncthreads();
         if (tid < F) {
             int st = x - c;
@@ -1427,7 +1429,7 @@ template <int W, int BS, int RPT> __device__ void partition_coarse(const Inst &I
             st_a0[j] = a0[e];
             if (W == 2) st_a1[W == 2 ? j : 0] = a1[e];
             st_v[j] = v[e];
-            st_d[j] = (unsigned char)lb[e];
+            st_d[j] = (Dst)lb[e];
         }
         __syncthreads();
         const int nr = min(NRND, n - r0);

@@ -97,6 +97,38 @@ def test_batch_instance_equals_oracle(orc):
             assert np.array_equal(g, o), f
 
 
+def test_batch_with_initiator_instances(orc):
+    """Instances with and without the initiator rule share one batch (the
+    merge launch takes the largest LDS size of its instances): each equals
+    its solo run, and the initiator instance equals the oracle's run with
+    the same threshold, bit for bit."""
+    fq = _fq()
+    specs = _real_specs()[:4]
+    specs[1] = dict(specs[1], initiator=3.0)
+    specs[3] = dict(specs[3], initiator=0.0)
+    steps = 400
+    _flush(f"[batch initiator] {len(specs)} instances, {steps} steps")
+    b = fq.Batch(specs)
+    for i, sp in enumerate(specs):
+        a = fq.start_address(sp["model"], sp["M"], sp["N"])
+        b.instance(i).set_state([a], [10.0], 0.0, 0, ref=a, yref=10.0)
+    st = b.run(steps)
+    b.close()
+    for i, sp in enumerate(specs):
+        assert st[i].tobytes() == _solo(sp, steps).tobytes(), i
+    sp = specs[1]
+    P = orc.params(0, sp["M"], sp["N"], 1.0, sp["u"], dtau=sp["dtau"], target=sp["target_walkers"],
+                   seed=sp["seed"], initiator=3.0)
+    a = orc.start_address(0, sp["M"], sp["N"])
+    ost, _, _ = orc.run(P, [a], [10.0], 0.0, 1, steps, a, 10.0)
+    for f in ost.dtype.names:
+        g, o = st[1][f], ost[f]
+        if g.dtype.kind == "f":
+            assert np.array_equal(g.view(np.uint64), o.view(np.uint64)), f
+        else:
+            assert np.array_equal(g, o), f
+
+
 def test_batch_momentum_equals_solo():
     fq = _fq()
     specs = [_spec(1, 8, 8, 4.0, 1e-3, 5e3, 21, 8192, 65536),

@@ -118,6 +118,9 @@ CASES = [
     (0, 12, 12, 6.0, 1e-3, 3000, 15, 1, 256, 2048, 512, 1.0),
     (0, 20, 20, 6.0, 1e-3, 3000, 16, 2, 128, 2048, 1024, 1.0),
     (1, 10, 10, 4.0, 1e-3, 2500, 17, 1, 128, 2048, 1024, 1.0),
+    # the most buckets: coarse groups of 512 buckets in the second pass
+    (0, 20, 20, 6.0, 1e-3, 3000, 18, 2, 32768, 1024, 512, 1.0),
+    (1, 10, 10, 4.0, 1e-3, 2500, 19, 1, 32768, 1024, 256, 1.0),
 ]
 
 
