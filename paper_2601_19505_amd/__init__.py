@@ -411,7 +411,8 @@ class Batch:
 
     `specs` is a list of dicts with the keyword arguments of Solver (model,
     M, N, t, u, dtau, target_walkers, seed, addr_words, threshold, t_rel,
-    table_capacity, spawn_capacity, buckets, lds_slots, block, spawn_block).
+    flags, initiator, table_capacity, spawn_capacity, buckets, lds_slots, block,
+    spawn_block).
     """
 
     def __init__(self, specs):
