@@ -73,10 +73,16 @@ def test_workspace_size_and_defaults():
                                 dict(g=float("nan")), dict(model=2, M=36, N=36, lx=6, W=1, u=1.0),
                                 dict(target=float("inf")), dict(target=0.0), dict(theta=float("nan")),
                                 dict(theta=0.0), dict(dtau=0.0), dict(dtau=float("inf")),
-                                dict(flags=128, n_a=-1.0), dict(flags=128, n_a=float("nan"))])
+                                dict(flags=128, n_a=-1.0), dict(flags=128, n_a=float("nan")),
+                                dict(buckets=65536)])
 def test_workspace_size_rejects_invalid(kw):
     with pytest.raises(fq.FqError):
         _ws(**kw)
+
+
+def test_largest_bucket_count_accepted():
+    n, lay = _ws(buckets=32768, slots=1024, block=512, table=10_000_000, spawn=40_000_000)
+    assert n > 0 and lay.buckets == 32768
 
 
 def test_initiator_threshold_accepted():
