@@ -441,9 +441,8 @@ int resolve(const fq_hamiltonian *h, const fq_params *p, const fq_layout *lin, R
     if (L.buckets == 0) {
         double uniq = (double)L.table_capacity + 0.25 * (double)L.spawn_capacity;
         i64 b = (i64)std::ceil(uniq / (0.55 * L.lds_slots));
-        L.buckets = (int)((i64)1 << ilog2(std::max<i64>(b, 1)));
+        L.buckets = (int)((i64)1 << ilog2(std::min<i64>(std::max<i64>(b, 1), MAX_BUCKETS)));
     }
-    if (L.buckets > MAX_BUCKETS) L.buckets = MAX_BUCKETS;
     if (L.buckets < 1 || (L.buckets & (L.buckets - 1)) || L.buckets > MAX_BUCKETS) {
         err = "buckets must be a power of two <= 32768";
         return FQ_EINVAL;
