@@ -273,6 +273,23 @@ constexpr int FIX_FRAC = 80;  // fractional bits of the fixed-point accumulators
 __device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf, int &inx)
 {
     u64 b = dbits(v);
+    {
+        // the common range 2^-27 <= |v| < 2^36 (the mantissa moves up by 1..63
+        // bits): exact, a 128-bit shift and a conditional negation.  Taken
+        // when every active lane of the wave is in it, so that no lane runs
+        // both forms; the general form below gives the same result there.
+        const u32 e0 = (u32)(b >> 52) & 0x7ffu;
+        if (__all(e0 - 996u < 63u)) {
+            const u64 m0 = (b & 0x000FFFFFFFFFFFFFull) | (1ull << 52);
+            const int s0 = (int)e0 - 995;
+            const u64 L0 = m0 << s0, H0 = m0 >> (64 - s0);
+            const u64 neg = b >> 63, sgn = 0ull - neg;
+            const u64 lx = L0 ^ sgn;
+            lo = lx + neg;
+            hi = (H0 ^ sgn) + (lo < lx ? 1ull : 0ull);
+            return;
+        }
+    }
     int e = (int)((b >> 52) & 0x7ff);
     u64 m = b & 0x000FFFFFFFFFFFFFull;
     if (e == 0x7ff) { ovf = 1; lo = hi = 0; return; }
