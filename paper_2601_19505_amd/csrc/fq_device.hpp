@@ -327,6 +327,26 @@ __device__ __forceinline__ void to_fixed(double v, u64 &lo, u64 &hi, int &ovf)
 // two's complement 128-bit fixed point -> nearest double (half-even)
 __device__ __forceinline__ double from_fixed(u64 lo, u64 hi)
 {
+    {
+        // the common range 2^-16 <= |value| < 2^36 (the high word of the
+        // magnitude is nonzero and below 2^52): the 53 leading bits come from
+        // the two words with one shift each and the rounding remainder lies in
+        // the low word.  Taken when every active lane of the wave is in it;
+        // the general form below gives the same result there.
+        const u64 sg = (u64)((i64)hi >> 63);  // all ones when negative
+        const u64 l = (lo ^ sg) - sg;         // the magnitude's words
+        const u64 h = (hi ^ sg) + ((sg != 0 && lo == 0) ? 1ull : 0ull);
+        if (__all(h != 0 && h < (1ull << 52))) {
+            const int s0 = 12 + msb(h);       // bits dropped: 12 .. 63
+            u64 mant = (h << (64 - s0)) | (l >> s0);
+            const u64 rem = l & ((1ull << s0) - 1), half = 1ull << (s0 - 1);
+            mant += (rem > half || (rem == half && (mant & 1ull))) ? 1ull : 0ull;
+            const int s1 = mant == (1ull << 53) ? s0 + 1 : s0;
+            mant = mant == (1ull << 53) ? mant >> 1 : mant;
+            const double r = bitsd(((u64)(s1 + 995) << 52) | (mant & 0x000FFFFFFFFFFFFFull));
+            return sg ? -r : r;
+        }
+    }
     bool neg = (i64)hi < 0;
     if (neg) { lo = ~lo + 1; hi = ~hi + (lo == 0 ? 1 : 0); }
     if ((lo | hi) == 0) return 0.0;
