@@ -52,12 +52,24 @@ __global__ __launch_bounds__(FIN_BS) void k_finalize(const Inst *const *insts)
 // runs that different workgroups append to one bucket's slab then meet in
 // that XCD's L2, which merges partial cache lines before they are written
 // back.
-// Threads per workgroup and records per thread and round, by address
-// words (measured: 512 x 4 for the 12- and 16-byte records of one-word
-// addresses, 1024 x 2 for the 24-byte records of two-word addresses).
+// Threads per workgroup and records per thread and round, by address words
+// (measured at both benchmark sizes: 1024 x 3 records per round is faster
+// than 2048 or 4096 per round, and than other shapes of 3072).
+#ifndef FQ_PART1_BS
+#define FQ_PART1_BS 1024
+#endif
+#ifndef FQ_PART1_RPT
+#define FQ_PART1_RPT 3
+#endif
+#ifndef FQ_PART2_BS
+#define FQ_PART2_BS 1024
+#endif
+#ifndef FQ_PART2_RPT
+#define FQ_PART2_RPT 3
+#endif
 template <int W> struct PartShape;
-template <> struct PartShape<1> { static constexpr int BS = 512, RPT = 4; };
-template <> struct PartShape<2> { static constexpr int BS = 1024, RPT = 2; };
+template <> struct PartShape<1> { static constexpr int BS = FQ_PART1_BS, RPT = FQ_PART1_RPT; };
+template <> struct PartShape<2> { static constexpr int BS = FQ_PART2_BS, RPT = FQ_PART2_RPT; };
 
 // FMAX: the most buckets per coarse group the workgroup splits into (256, or
 // 512 with more than 16384 buckets)
