@@ -8,7 +8,7 @@
 #pragma once
 #include "fq_step.hpp"
 
-// // The step kernels run over a set of instances: one, or a batch.  `insts` is
+// The step kernels run over a set of instances: one, or a batch.  `insts` is
 // a device array of instance descriptors.  A merge or spawn workgroup finds
 // its instance and bucket through `map` (entry = instance << 15 | bucket);
 // without a map there is one instance and workgroup b takes bucket b.

@@ -5,7 +5,9 @@
 //             address word 1 (W = 2), value (f64); count per bucket.
 //   slab[p]:  B buckets x cap_s spawn records (array of structs: address
 //             words + value; 12 B when the address fits 32 bits, else 16 B
-//             for W = 1, 24 B for W = 2); count per bucket.
+//             for W = 1, 24 B for W = 2; with the initiator rule a record of
+//             a non-initiator parent carries a flag bit above the address
+//             bits); count per bucket.
 // An address lives in bucket bucket_index(address): the top log2 B bits of
 // a hash of the address.
 //
@@ -21,8 +23,8 @@
 //   4. compact survivors into table[1-p] and into LDS;
 //   5. spawn for step n+2 from every survivor (a separate kernel): exact
 //      columns when |c| >= t_rel m, attempt by attempt over the workgroup;
-//      else ceil|c| Philox picks, in units of up to 8 attempts of one parent
-//      per thread.  Records are partitioned in rounds: every thread holds
+//      else ceil|c| Philox picks, in units of four consecutive attempts of
+//      one parent per thread.  Records are partitioned in rounds: every thread holds
 //      its round's records in registers, takes a rank inside each record's
 //      destination group with an LDS atomic, one global atomic per group
 //      reserves a contiguous run, and the records are stored into the runs.
